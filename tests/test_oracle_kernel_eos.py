@@ -1,0 +1,130 @@
+"""Pins of the oracle's smoothing kernel and equation of state.
+
+The paper prints none of these formulas (it defers them to its ref. [11]);
+the checks below fix them by closed forms and invariants that do not reuse the
+oracle's own expressions: the 3-D integral of W, the derivative relation
+between W and F, compact support, the Tait law's zero and its derivative.
+"""
+
+import math
+
+import numpy as np
+import pytest
+from scipy import integrate
+
+from sph_inputs import physics
+
+
+@pytest.fixture(params=[0, 1], ids=["wendland", "cubic"])
+def P(request, ora):
+    ph = physics(0.01, kernel=request.param)
+    return ora.params(ph)
+
+
+def test_kernel_integrates_to_one(ora, P):
+    # int_R^3 W dV = int_0^{2h} 4 pi r^2 W(r) dr = 1  (normalisation)
+    h = P.h
+    val, err = integrate.quad(lambda r: 4 * math.pi * r * r * ora.kernel_w(P, r), 0.0, 2 * h,
+                              points=[h], epsabs=1e-14, epsrel=1e-12, limit=200)
+    assert abs(val - 1.0) < 1e-10
+
+
+def test_gradient_factor_is_dW_dr_over_r(ora, P):
+    # grad_a W_ab = F r_ab  <=>  F(r) r = dW/dr ; central differences of W
+    h = P.h
+    for q in [0.05, 0.3, 0.7, 0.99, 1.01, 1.5, 1.9, 1.999]:
+        r = q * h
+        e = 1e-6 * h
+        dwdr = (ora.kernel_w(P, r + e) - ora.kernel_w(P, r - e)) / (2 * e)
+        assert ora.kernel_f(P, r) * r == pytest.approx(dwdr, rel=1e-6, abs=1e-9 / h**4)
+    # W decreases monotonically: F < 0 inside the support
+    assert all(ora.kernel_f(P, q * h) < 0 for q in np.linspace(0.01, 1.99, 50))
+
+
+def test_compact_support(ora, P):
+    h = P.h
+    for q in [2.0, 2.0 + 1e-12, 2.5, 10.0]:
+        assert ora.kernel_w(P, q * h) == 0.0
+        assert ora.kernel_f(P, q * h) == 0.0
+    # continuous at the edge of the support
+    assert ora.kernel_w(P, 2 * h * (1 - 1e-9)) < 1e-20 / h**3
+    assert abs(ora.kernel_f(P, 2 * h * (1 - 1e-6))) < 1e-9 / h**5
+
+
+def _lattice_vectors(h, dp):
+    m = int(math.ceil(2 * h / dp)) + 1
+    r = np.arange(-m, m + 1) * dp
+    g = np.stack(np.meshgrid(r, r, r, indexing="ij"), axis=-1).reshape(-1, 3)
+    d = np.linalg.norm(g, axis=1)
+    return g[(d < 2 * h) & (d > 0)], d[(d < 2 * h) & (d > 0)]
+
+
+def test_lattice_sums(ora, P):
+    # On the cubic lattice with h = 1.2 sqrt(3) dp the SPH sums reproduce their
+    # continuum values to < 1e-3: sum_b W dp^3 -> 1 (with the self term),
+    # sum_b grad W -> 0 exactly (symmetry), and the gradient-consistency matrix
+    # sum_b (x_b - x_a) (x) grad_a W_ab dp^3 -> identity.
+    dp = 0.01
+    vec, d = _lattice_vectors(P.h, dp)
+    W = np.array([ora.kernel_w(P, r) for r in d])
+    F = np.array([ora.kernel_f(P, r) for r in d])
+    norm = (W.sum() + ora.kernel_w(P, 0.0)) * dp**3
+    assert abs(norm - 1.0) < 1e-3
+    # r_ab = x_a - x_b = -vec
+    grad = (F[:, None] * (-vec)).sum(0)
+    assert np.abs(grad).max() < 1e-9 * np.abs(F).max() * dp
+    M = (vec[:, :, None] * (F[:, None] * (-vec))[:, None, :]).sum(0) * dp**3
+    assert np.allclose(np.diag(M), np.diag(M)[0], rtol=1e-12)
+    assert abs(M[0, 0] - 1.0) < 1e-3
+    off = M - np.diag(np.diag(M))
+    assert np.abs(off).max() < 1e-12
+
+
+def test_lattice_neighbour_count_matches_paper(ora):
+    # Section 2: each particle has more than 250 neighbours.  With support 2h
+    # and h = 1.2 sqrt(3) dp, the interior lattice count is the number of
+    # integer vectors with 0 < |k|^2 < (2h/dp)^2 -- counted here in integers.
+    import json, os
+
+    facts = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_facts.json")))
+    lower = [f for f in facts["facts"] if f["name"] == "min_neighbours_per_particle"][0]["value"]
+    ph = physics(0.01)
+    lim = (2 * ph.h / ph.dp) ** 2
+    m = 5
+    cnt = sum(1 for i in range(-m, m + 1) for j in range(-m, m + 1) for k in range(-m, m + 1)
+              if 0 < i * i + j * j + k * k < lim)
+    assert cnt == 304
+    assert cnt > lower
+    # support = h instead would contradict the paper
+    lim_h = (ph.h / ph.dp) ** 2
+    cnt_h = sum(1 for i in range(-m, m + 1) for j in range(-m, m + 1) for k in range(-m, m + 1)
+                if 0 < i * i + j * j + k * k < lim_h)
+    assert cnt_h < lower
+
+
+def test_tait_eos(ora):
+    ph = physics(0.01)
+    P = ora.params(ph)
+    assert ora.pressure(P, ph.rho0) == 0.0
+    assert ora.sound(P, ph.rho0) == pytest.approx(ph.c0, rel=1e-15)
+    # the sound speed is sqrt(dP/drho): central differences of P
+    for rho in [980.0, 1000.0, 1003.0, 1010.0, 1050.0]:
+        e = 1e-4
+        dpdr = (ora.pressure(P, rho + e) - ora.pressure(P, rho - e)) / (2 * e)
+        assert ora.sound(P, rho) ** 2 == pytest.approx(dpdr, rel=1e-8)
+    # compression raises pressure, expansion gives tension
+    assert ora.pressure(P, 1001.0) > 0 > ora.pressure(P, 999.0)
+
+
+def test_hydrostatic_initial_density(ora):
+    # The layouts set fluid density so that the Tait pressure equals
+    # rho0 |g| (H - z): checks the generator's inverse against the oracle EOS.
+    from sph_inputs import named_case
+
+    L = named_case("cfg1")
+    P = ora.params(L.phys)
+    H = L.meta["H"]
+    idx = np.arange(L.nb, L.n, 97)
+    for i in idx:
+        expect = L.phys.rho0 * 9.81 * (H - L.x[i, 2])
+        assert ora.pressure(P, L.rho[i]) == pytest.approx(expect, rel=1e-9, abs=1e-9)
