@@ -1,0 +1,215 @@
+/*
+ * sph.h -- C ABI of the MI355X (gfx950) WCSPH particle-interaction library.
+ *
+ * The library implements one time step of the weakly compressible SPH method
+ * of Domínguez, Crespo & Gómez-Gesteira, "Optimization strategies for parallel
+ * CPU and GPU implementations of a meshfree particle method" (Section 2: each
+ * step is NL -> PI -> SU), as hand-written HIP kernels:
+ *
+ *   sph_build_cells        NL: cell key, stable radix sort, cell ranges,
+ *                          reorder of the particle arrays (Section 4.1).
+ *   sph_interact           PI: F-F + F-B interactions of fluid targets and
+ *                          B-F interactions of boundary targets (Sections 2,
+ *                          4.3-4.5; Table 1 formulation).
+ *   sph_step               SU: variable time step from global maxima and the
+ *                          Verlet update (Section 4.1, Table 1).
+ *   sph_interact_backward  vector-Jacobian product of sph_interact (no
+ *                          counterpart in the paper).
+ *   sph_encode/sph_decode  FP64 <-> device state conversion.
+ *
+ * Conventions shared by every entry point
+ *   - Every array argument is a DEVICE pointer owned by the caller; struct
+ *     arguments (sph_grid, sph_params, sph_state, sph_cells) are host structs
+ *     whose array members are device pointers.  The library allocates no
+ *     memory and keeps no global state; it is re-entrant.
+ *   - Work is enqueued on `stream` and the call returns without
+ *     synchronising.  Host-side validation returns a status immediately and
+ *     enqueues nothing on failure.  Conditions found on the device are OR-ed
+ *     into the caller-owned bitmask *dev_status (read it after a sync).
+ *   - `ws`/`ws_bytes`: one caller-owned device workspace of at least
+ *     sph_workspace_bytes(grid, n) bytes, shared by all calls of a simulation.
+ *     Calls that share a workspace must be ordered on one stream.
+ *   - Sorted-state layout: boundary particles occupy slots [0, nb) and fluid
+ *     particles [nb, n); excluded particles (outside the domain) are the last
+ *     slots of the fluid range.
+ *
+ * Positions are an integer cell plus an FP32 offset from the cell centre:
+ *   x = origin + (k + 1/2) * cell + offset  (per axis), |offset| <= cell/2,
+ * so relative distances keep FP32 accuracy in large domains.  Pair
+ * arithmetic is FP32 with FP32 accumulation; the position update and the
+ * time-step reduction are FP64.
+ */
+#ifndef SPH_H_
+#define SPH_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SPH_ABI_VERSION 1
+#define SPH_API __attribute__((visibility("default")))
+#define SPH_EXCLUDED INT32_MAX /* cell index of a particle outside the domain */
+
+typedef enum {
+    SPH_OK = 0,
+    SPH_ERR_ARG = 1,       /* invalid argument (null pointer, bad size, bad grid) */
+    SPH_ERR_WORKSPACE = 2, /* ws_bytes smaller than sph_workspace_bytes()        */
+    SPH_ERR_HIP = 3        /* a kernel launch failed (hipGetLastError)            */
+} sph_status;
+
+/* bits OR-ed into *dev_status by the kernels */
+enum {
+    SPH_DEV_OUT_OF_GRID = 1, /* a particle left the domain and is now excluded */
+    SPH_DEV_NONFINITE = 2    /* non-finite acceleration/time step; state kept  */
+};
+
+/* Cell grid of the neighbour list (Section 2: domain divided into cells so the
+ * search covers the own and adjacent cells; Section 3.2: cells of side
+ * support/n; Section 4.4: cells ordered X fastest, then Y, then Z).
+ * The stencil is (2*nsub+1)^3 cells, read as (2*nsub+1)^2 X-runs. */
+typedef struct {
+    double origin[3]; /* lower corner of cell (0,0,0) = lower corner of the domain  */
+    double hi[3];     /* upper corner of the domain; outside [origin, hi) = excluded */
+    double cell;      /* cell side; requires nsub * cell >= 2h (1 + 2^-21)           */
+    int32_t nc[3];    /* cells per axis; ncell = nc0*nc1*nc2 < 2^30 - 1             */
+    int32_t nsub;     /* 1 (cell = support 2h) or 2 (cell = h)                       */
+} sph_grid;
+
+/* Physical constants (Table 1: Verlet, variable time step, Monaghan artificial
+ * viscosity, Tait equation of state, dynamic boundaries). */
+typedef struct {
+    double h;        /* smoothing length; kernel support is 2h                   */
+    double rho0;     /* reference density                                        */
+    double gamma;    /* Tait exponent; must be 7                                 */
+    double c0;       /* reference sound speed; Tait B = c0^2 rho0 / gamma        */
+    double alpha;    /* artificial-viscosity coefficient                         */
+    double eta2;     /* regulariser of mu_ab = h v.r / (r^2 + eta2)              */
+    double g[3];     /* gravity, applied to fluid particles                      */
+    double mass;     /* particle mass (fluid and boundary)                       */
+    double cfl;      /* Courant factor of the variable time step                 */
+    int32_t kernel;  /* 0 = Wendland quintic (the only kernel built so far)      */
+    int32_t verlet_ns;   /* corrective Verlet step every verlet_ns steps (>= 1)  */
+    int32_t bound_floor; /* 1: boundary density floored at rho0 after each step  */
+    int32_t pad_;
+} sph_params;
+
+/* Particle state (structure of arrays); one instance per side of a double
+ * buffer.  All members are device arrays of length n (x4 where noted). */
+typedef struct {
+    int32_t n;            /* particles                                              */
+    int32_t nb;           /* boundary particles (slots [0, nb))                     */
+    int32_t *cell;        /* [n] linear cell index kx + nc0 (ky + nc1 kz), or SPH_EXCLUDED */
+    float *pos;           /* [4n] (ox, oy, oz, P/rho^2): offset from the cell centre */
+    float *velrho;        /* [4n] (vx, vy, vz, rho - rho0) at level n               */
+    float *velrho_prev;   /* [4n] the same at level n-1 (Verlet)                     */
+    int32_t *id;          /* [n] original particle id                               */
+} sph_state;
+
+/* Output of the neighbour list (CellBeginEnd of Section 4.1, stored as one
+ * prefix array).  Keys: boundary cell k -> k, fluid cell k -> ncell + k,
+ * excluded -> 2 ncell. */
+typedef struct {
+    int32_t *start; /* [2*ncell + 2]: start[key] = first sorted slot with that key or a
+                       larger one; particles of key k are [start[k], start[k+1])         */
+    int32_t *list;  /* [n] non-empty keys in ascending order (boundary cells first)      */
+    int32_t *info;  /* [4] (device): non-empty boundary cells, non-empty fluid cells,
+                       excluded particles, reserved                                     */
+} sph_cells;
+
+/* Adjoint buffers of one Verlet step (device, [4n] each, sorted slot order). */
+typedef struct {
+    float *pos_bar;         /* in: adjoint of x^{n+1} (xyz; w unused); out: of x^n       */
+    float *velrho_bar;      /* in: adjoint of (v, rho)^{n+1};   out: of (v, rho)^n      */
+    float *velrho_prev_bar; /* in: adjoint of the stored level-n copy; out: of level n-1 */
+    float *ace_bar;         /* out: adjoint of (a, drho/dt)^n                             */
+} sph_adjoint;
+
+/* Size in bytes of the workspace needed by all calls for n particles on
+ * grid g; 0 if the arguments are invalid. */
+SPH_API size_t sph_workspace_bytes(const sph_grid *g, int32_t n);
+
+/* ABI version of the loaded library (SPH_ABI_VERSION). */
+SPH_API int32_t sph_abi_version(void);
+
+/* Fill a state from FP64 host-order arrays already on the device (x [3n],
+ * v [3n], rho [n]; ids [0, nb) are boundary particles).  Position encoding:
+ * d = x - origin, k = floor(d / cell), offset = fp32(fma(-(k + 1/2), cell, d));
+ * a particle outside [origin, hi) gets cell SPH_EXCLUDED and sets
+ * SPH_DEV_OUT_OF_GRID.  velrho_prev = velrho, pos.w = P/rho^2, id = index. */
+SPH_API sph_status sph_encode(const sph_grid *g, const sph_params *p, const double *x,
+                      const double *v, const double *rho, sph_state *st, int32_t *dev_status,
+                      hipStream_t stream);
+
+/* Decode a state to FP64 arrays in slot order: x = fma(k + 1/2, cell, origin)
+ * + offset, v, rho = rho0 + (rho - rho0); NaN positions for excluded slots. */
+SPH_API sph_status sph_decode(const sph_grid *g, const sph_params *p, const sph_state *st, double *x,
+                      double *v, double *rho, hipStream_t stream);
+
+/* NL (Section 4.1): key = (slot < nb ? 0 : ncell) + cell, or 2 ncell when
+ * excluded; stable LSD radix sort of (key, slot), ties keeping the src order;
+ * cell ranges and the list of non-empty keys; gather of every state array
+ * into dst in sorted order.  perm[i] = src slot of dst slot i.  src and dst
+ * must not overlap.  dst->n and dst->nb are set from src. */
+SPH_API sph_status sph_build_cells(const sph_grid *g, const sph_state *src, sph_state *dst,
+                           sph_cells *cells, int32_t *perm, void *ws, size_t ws_bytes,
+                           int32_t *dev_status, hipStream_t stream);
+
+/* PI (Section 2 interaction classes F-F, F-B, B-F; never B-B).  For a fluid
+ * target a and every b != a within the support (r_ab^2 < 4 h^2, decided in
+ * FP32 from the encoded positions):
+ *   ace[a].xyz = g - m sum_b (P_a/rho_a^2 + P_b/rho_b^2 + Pi_ab) F_ab r_ab
+ *   ace[a].w   = m sum_b (v_a - v_b).r_ab F_ab              (drho/dt)
+ *   visc[a]    = max_b |mu_ab|
+ * with grad_a W_ab = F_ab r_ab (Wendland quintic), mu_ab = h v_ab.r_ab /
+ * (r^2 + eta2), Pi_ab = -alpha cbar mu_ab / rhobar when v_ab.r_ab < 0 else 0,
+ * Tait P = B((rho/rho0)^7 - 1), c = c0 (rho/rho0)^3.  Boundary targets get
+ * (0, 0, 0, drho/dt) over fluid neighbours and visc 0; excluded slots get 0.
+ * parts: SPH_PI_FLUID and/or SPH_PI_BOUNDARY (each enqueues one pair kernel
+ * plus a one-wave counter reset; a full stage is SPH_PI_ALL).
+ * npairs (may be NULL): += number of directed interacting pairs (u64).
+ * nbr_stats (may be NULL, diagnostic, slower): [2n] per slot (neighbour
+ * count, sum over neighbours of uint32(id * 2654435761)). */
+#define SPH_PI_FLUID 1u    /* fluid targets: F-F + F-B (Section 4.5 fused kernel) */
+#define SPH_PI_BOUNDARY 2u /* boundary targets: B-F, plus zeroing of excluded slots */
+#define SPH_PI_ALL 3u
+SPH_API sph_status sph_interact(const sph_grid *g, const sph_params *p, const sph_state *st,
+                        const sph_cells *cells, unsigned parts, float *ace, float *visc,
+                        unsigned long long *npairs, int32_t *nbr_stats, void *ws,
+                        size_t ws_bytes, hipStream_t stream);
+
+#define SPH_FIXED_DT 1u /* use *dt as given instead of the CFL time step      */
+#define SPH_ADJOINT 2u  /* run the transpose of the Verlet map (needs adj)    */
+
+/* SU (Section 4.1, Table 1).  Time step (FP64 reduction over fluid slots):
+ *   dt = cfl * min( sqrt(h / max|a|), h / max(c + visc) ),
+ * written to dt[0] (device) unless SPH_FIXED_DT.  Verlet: regular step
+ *   x += dt v + dt^2/2 a,  (v, rho)^{n+1} = (v, rho)^{n-1} + 2 dt (a, D),
+ * corrective step when step == 0 or (step + 1) % verlet_ns == 0:
+ *   (v, rho)^{n+1} = (v, rho)^n + dt (a, D);
+ * the position update is FP64 and re-bins (cell, offset).  Boundary slots
+ * keep position and velocity; their density follows the same rule and is
+ * floored at rho0 if bound_floor.  Unless SPH_FIXED_DT, a non-finite value
+ * in ace or visc (any slot) or a non-finite time step sets SPH_DEV_NONFINITE,
+ * writes NaN to dt[0] and leaves the state unchanged.
+ * Adjoint mode: see sph_adjoint (not built yet: returns SPH_ERR_ARG). */
+SPH_API sph_status sph_step(const sph_grid *g, const sph_params *p, sph_state *st, const float *ace,
+                    const float *visc, double *dt, long long step, unsigned flags,
+                    sph_adjoint *adj, void *ws, size_t ws_bytes, int32_t *dev_status,
+                    hipStream_t stream);
+
+/* VJP of sph_interact at state st (not built yet: returns SPH_ERR_ARG). */
+SPH_API sph_status sph_interact_backward(const sph_grid *g, const sph_params *p, const sph_state *st,
+                                 const sph_cells *cells, const float *ace_bar, float *pos_bar,
+                                 float *velrho_bar, double *alpha_bar, void *ws,
+                                 size_t ws_bytes, hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SPH_H_ */

@@ -1,0 +1,155 @@
+// api.hip -- the extern "C" entry points: host-side validation, workspace
+// layout and the calls into the per-stage launchers.
+#include <math.h>
+
+#include "sph_internal.h"
+
+using namespace sph;
+
+namespace {
+
+bool grid_ok(const sph_grid *g)
+{
+    if (!g) return false;
+    if (g->nsub != 1 && g->nsub != 2) return false;
+    if (!(g->cell > 0.0) || !isfinite(g->cell)) return false;
+    for (int d = 0; d < 3; ++d) {
+        if (g->nc[d] <= 0) return false;
+        if (!isfinite(g->origin[d]) || !isfinite(g->hi[d]) || !(g->hi[d] > g->origin[d]))
+            return false;
+        // the grid must cover the domain
+        if ((double)g->nc[d] * g->cell < g->hi[d] - g->origin[d]) return false;
+    }
+    const int64_t ncell = ncell_of(g);
+    return ncell > 0 && ncell < (1 << 30) - 1;
+}
+
+bool params_ok(const sph_grid *g, const sph_params *p)
+{
+    if (!p) return false;
+    if (!(p->h > 0.0) || !(p->rho0 > 0.0) || !(p->c0 > 0.0) || !(p->mass > 0.0)) return false;
+    if (p->gamma != 7.0) return false;
+    if (p->kernel != 0) return false;
+    if (p->verlet_ns < 1) return false;
+    if (!(p->eta2 > 0.0) || !(p->alpha >= 0.0) || !(p->cfl > 0.0)) return false;
+    // the (2 nsub + 1)^3 stencil must cover the support 2h, with margin for
+    // FP32 rounding of the offsets
+    if (g->nsub * g->cell < 2.0 * p->h * (1.0 + ldexp(1.0, -21))) return false;
+    return true;
+}
+
+bool state_ok(const sph_state *st, bool with_arrays = true)
+{
+    if (!st) return false;
+    if (st->n < 0 || st->nb < 0 || st->nb > st->n) return false;
+    if (with_arrays && st->n > 0 &&
+        (!st->cell || !st->pos || !st->velrho || !st->velrho_prev || !st->id))
+        return false;
+    return true;
+}
+
+bool cells_ok(const sph_cells *c)
+{
+    return c && c->start && c->list && c->info;
+}
+
+sph_status ws_check(const sph_grid *g, int32_t n, void *ws, size_t ws_bytes, Workspace *w)
+{
+    layout_workspace(g, n, nullptr, w);
+    if (!ws || ws_bytes < w->bytes) return SPH_ERR_WORKSPACE;
+    layout_workspace(g, n, ws, w);
+    return SPH_OK;
+}
+
+sph_status hip_status(hipError_t e) { return e == hipSuccess ? SPH_OK : SPH_ERR_HIP; }
+
+}  // namespace
+
+extern "C" {
+
+int32_t sph_abi_version(void) { return SPH_ABI_VERSION; }
+
+size_t sph_workspace_bytes(const sph_grid *g, int32_t n)
+{
+    if (!grid_ok(g) || n < 0) return 0;
+    Workspace w;
+    layout_workspace(g, n, nullptr, &w);
+    return w.bytes;
+}
+
+sph_status sph_encode(const sph_grid *g, const sph_params *p, const double *x, const double *v,
+                      const double *rho, sph_state *st, int32_t *dev_status, hipStream_t stream)
+{
+    if (!grid_ok(g) || !params_ok(g, p) || !state_ok(st) || !dev_status) return SPH_ERR_ARG;
+    if (st->n > 0 && (!x || !v || !rho)) return SPH_ERR_ARG;
+    return hip_status(launch_encode(g, p, x, v, rho, st, dev_status, stream));
+}
+
+sph_status sph_decode(const sph_grid *g, const sph_params *p, const sph_state *st, double *x,
+                      double *v, double *rho, hipStream_t stream)
+{
+    if (!grid_ok(g) || !params_ok(g, p) || !state_ok(st)) return SPH_ERR_ARG;
+    if (st->n > 0 && (!x || !v || !rho)) return SPH_ERR_ARG;
+    return hip_status(launch_decode(g, p, st, x, v, rho, stream));
+}
+
+sph_status sph_build_cells(const sph_grid *g, const sph_state *src, sph_state *dst,
+                           sph_cells *cells, int32_t *perm, void *ws, size_t ws_bytes,
+                           int32_t *dev_status, hipStream_t stream)
+{
+    if (!grid_ok(g) || !state_ok(src) || !dst || !cells_ok(cells) || !dev_status) return SPH_ERR_ARG;
+    if (src->n > 0 && (!perm || !dst->cell || !dst->pos || !dst->velrho || !dst->velrho_prev ||
+                       !dst->id))
+        return SPH_ERR_ARG;
+    if (src->n > 0 && (src->cell == dst->cell || src->pos == dst->pos ||
+                       src->velrho == dst->velrho || src->velrho_prev == dst->velrho_prev ||
+                       src->id == dst->id))
+        return SPH_ERR_ARG;
+    Workspace w;
+    const sph_status ws_st = ws_check(g, src->n, ws, ws_bytes, &w);
+    if (ws_st != SPH_OK) return ws_st;
+    return hip_status(launch_build_cells(g, src, dst, cells, perm, w, dev_status, stream));
+}
+
+sph_status sph_interact(const sph_grid *g, const sph_params *p, const sph_state *st,
+                        const sph_cells *cells, unsigned parts, float *ace, float *visc,
+                        unsigned long long *npairs, int32_t *nbr_stats, void *ws,
+                        size_t ws_bytes, hipStream_t stream)
+{
+    if (!grid_ok(g) || !params_ok(g, p) || !state_ok(st) || !cells_ok(cells)) return SPH_ERR_ARG;
+    if (parts == 0 || (parts & ~SPH_PI_ALL)) return SPH_ERR_ARG;
+    if (st->n > 0 && (!ace || !visc)) return SPH_ERR_ARG;
+    Workspace w;
+    const sph_status ws_st = ws_check(g, st->n, ws, ws_bytes, &w);
+    if (ws_st != SPH_OK) return ws_st;
+    return hip_status(launch_interact(g, p, st, cells, parts, ace, visc, npairs, nbr_stats, w, stream));
+}
+
+sph_status sph_step(const sph_grid *g, const sph_params *p, sph_state *st, const float *ace,
+                    const float *visc, double *dt, long long step, unsigned flags,
+                    sph_adjoint *adj, void *ws, size_t ws_bytes, int32_t *dev_status,
+                    hipStream_t stream)
+{
+    if (!grid_ok(g) || !params_ok(g, p) || !state_ok(st) || !dt || !dev_status || step < 0)
+        return SPH_ERR_ARG;
+    if (flags & ~(SPH_FIXED_DT | SPH_ADJOINT)) return SPH_ERR_ARG;
+    if (flags & SPH_ADJOINT) return SPH_ERR_ARG;  // adjoint mode not built yet
+    (void)adj;
+    if (st->n > 0 && (!ace || (!(flags & SPH_FIXED_DT) && !visc))) return SPH_ERR_ARG;
+    Workspace w;
+    const sph_status ws_st = ws_check(g, st->n, ws, ws_bytes, &w);
+    if (ws_st != SPH_OK) return ws_st;
+    return hip_status(launch_step(g, p, st, ace, visc, dt, step, flags, w, dev_status, stream));
+}
+
+sph_status sph_interact_backward(const sph_grid *g, const sph_params *p, const sph_state *st,
+                                 const sph_cells *cells, const float *ace_bar, float *pos_bar,
+                                 float *velrho_bar, double *alpha_bar, void *ws,
+                                 size_t ws_bytes, hipStream_t stream)
+{
+    (void)g; (void)p; (void)st; (void)cells; (void)ace_bar; (void)pos_bar; (void)velrho_bar;
+    (void)alpha_bar; (void)ws; (void)ws_bytes; (void)stream;
+    return SPH_ERR_ARG;  // not built yet
+}
+
+}  // extern "C"

@@ -1,0 +1,347 @@
+// build_cells.hip -- neighbour-list stage (Section 4.1): cell keys, a stable
+// LSD radix sort of (key, slot), the cell start array, the list of non-empty
+// keys and the reorder of every particle array into cell order.
+//
+// Keys: boundary cell k -> k, fluid cell k -> ncell + k, excluded -> 2 ncell,
+// so the sorted order is boundary cells, then fluid cells, then excluded
+// particles, each cell contiguous and cells X fastest (the X-run property
+// used by the interaction stencil, Section 4.4).
+#include "sph_internal.h"
+
+namespace sph {
+
+// ---------------------------------------------------------------------------
+// keys
+
+__global__ void k_keys(int32_t n, int32_t nb, int32_t ncell, const int32_t *__restrict__ cell,
+                       uint32_t *__restrict__ keys, uint32_t *__restrict__ vals)
+{
+    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int32_t c = cell[i];
+    uint32_t k;
+    if (c == SPH_EXCLUDED) k = 2u * (uint32_t)ncell;
+    else k = (uint32_t)c + (i < nb ? 0u : (uint32_t)ncell);
+    keys[i] = k;
+    vals[i] = (uint32_t)i;
+}
+
+// ---------------------------------------------------------------------------
+// radix sort: per-block digit histograms, digit-major so that one exclusive
+// scan gives every (digit, block) its global output offset.
+
+__global__ __launch_bounds__(kSortThreads) void k_radix_hist(int32_t n, int shift,
+                                                             const uint32_t *__restrict__ keys,
+                                                             uint32_t *__restrict__ hist,
+                                                             int nblk)
+{
+    __shared__ uint32_t h[kRadix];
+    for (int d = threadIdx.x; d < kRadix; d += kSortThreads) h[d] = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * kSortTile;
+    for (int j = 0; j < kSortItems; ++j) {
+        const int64_t e = base + (int64_t)j * kSortThreads + threadIdx.x;
+        if (e < n) atomicAdd(&h[(keys[e] >> shift) & (kRadix - 1)], 1u);
+    }
+    __syncthreads();
+    for (int d = threadIdx.x; d < kRadix; d += kSortThreads)
+        hist[(int64_t)d * nblk + blockIdx.x] = h[d];
+}
+
+// Stable scatter.  The tile is processed in kSortItems rounds of one key per
+// thread; element order inside the tile is (round, thread), i.e. ascending
+// input index.  Within a wave, equal digits are ranked with ballots; across
+// waves through per-wave digit counts in LDS; across rounds through running
+// digit counters.
+__global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
+    int32_t n, int shift, const uint32_t *__restrict__ keys_in, const uint32_t *__restrict__ vals_in,
+    uint32_t *__restrict__ keys_out, uint32_t *__restrict__ vals_out,
+    const uint32_t *__restrict__ offs, int nblk)
+{
+    constexpr int NW = kSortThreads / kWave;
+    __shared__ uint32_t base_off[kRadix];
+    __shared__ uint32_t wcount[NW][kRadix];
+    const int t = threadIdx.x;
+    const int w = t / kWave;
+    for (int d = t; d < kRadix; d += kSortThreads) base_off[d] = offs[(int64_t)d * nblk + blockIdx.x];
+    const int64_t tile = (int64_t)blockIdx.x * kSortTile;
+    for (int j = 0; j < kSortItems; ++j) {
+        for (int d = t; d < NW * kRadix; d += kSortThreads) (&wcount[0][0])[d] = 0;
+        __syncthreads();
+        const int64_t e = tile + (int64_t)j * kSortThreads + t;
+        const bool valid = e < n;
+        uint32_t key = 0, val = 0, dig = 0;
+        if (valid) {
+            key = keys_in[e];
+            val = vals_in[e];
+            dig = (key >> shift) & (kRadix - 1);
+        }
+        unsigned long long peers = ballot(valid);
+        for (int b = 0; b < kRadixBits; ++b) {
+            const bool bit = (dig >> b) & 1u;
+            const unsigned long long m = ballot(bit);
+            peers &= bit ? m : ~m;
+        }
+        const unsigned rank_w = lane_rank(peers);
+        if (valid && rank_w == 0) wcount[w][dig] = (uint32_t)__popcll(peers);
+        __syncthreads();
+        if (valid) {
+            uint32_t pos = base_off[dig] + rank_w;
+            for (int ww = 0; ww < w; ++ww) pos += wcount[ww][dig];
+            keys_out[pos] = key;
+            vals_out[pos] = val;
+        }
+        __syncthreads();
+        for (int d = t; d < kRadix; d += kSortThreads) {
+            uint32_t s = 0;
+            for (int ww = 0; ww < NW; ++ww) s += wcount[ww][d];
+            base_off[d] += s;
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// exclusive scan (reduce -> scan partials -> apply), in place
+
+template <typename T>
+__device__ T block_exclusive_scan(T v, T *sh, T *total)
+{
+    // sh: kScanThreads entries
+    const int t = threadIdx.x;
+    sh[t] = v;
+    __syncthreads();
+    for (int off = 1; off < kScanThreads; off <<= 1) {
+        T add = t >= off ? sh[t - off] : (T)0;
+        __syncthreads();
+        sh[t] += add;
+        __syncthreads();
+    }
+    const T incl = sh[t];
+    *total = sh[kScanThreads - 1];
+    __syncthreads();
+    return incl - v;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kScanThreads) void k_scan_reduce(int64_t len, const T *__restrict__ a,
+                                                              unsigned long long *__restrict__ part)
+{
+    __shared__ T sh[kScanThreads];
+    const int64_t base = (int64_t)blockIdx.x * kScanTile;
+    T s = 0;
+    for (int j = 0; j < kScanItems; ++j) {
+        const int64_t e = base + (int64_t)j * kScanThreads + threadIdx.x;
+        if (e < len) s += a[e];
+    }
+    T tot;
+    block_exclusive_scan<T>(s, sh, &tot);
+    if (threadIdx.x == 0) part[blockIdx.x] = (unsigned long long)tot;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_partials(int64_t np,
+                                                                unsigned long long *__restrict__ part)
+{
+    __shared__ unsigned long long sh[kScanThreads];
+    unsigned long long carry = 0;
+    for (int64_t base = 0; base < np; base += (int64_t)kScanThreads * kScanItems) {
+        // each thread scans kScanItems consecutive partials serially
+        unsigned long long loc[kScanItems];
+        unsigned long long s = 0;
+        const int64_t first = base + (int64_t)threadIdx.x * kScanItems;
+        for (int j = 0; j < kScanItems; ++j) {
+            const int64_t e = first + j;
+            loc[j] = e < np ? part[e] : 0ull;
+            s += loc[j];
+        }
+        unsigned long long tot;
+        const unsigned long long ex = block_exclusive_scan<unsigned long long>(s, sh, &tot);
+        unsigned long long run = carry + ex;
+        for (int j = 0; j < kScanItems; ++j) {
+            const int64_t e = first + j;
+            if (e < np) part[e] = run;
+            run += loc[j];
+        }
+        carry += tot;
+        __syncthreads();
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kScanThreads) void k_scan_apply(int64_t len, T *__restrict__ a,
+                                                             const unsigned long long *__restrict__ part)
+{
+    // blocked: thread t owns kScanItems consecutive elements
+    __shared__ T sh[kScanThreads];
+    const int64_t first = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+    T loc[kScanItems];
+    T s = 0;
+    for (int j = 0; j < kScanItems; ++j) {
+        const int64_t e = first + j;
+        loc[j] = e < len ? a[e] : (T)0;
+        s += loc[j];
+    }
+    T tot;
+    const T ex = block_exclusive_scan<T>(s, sh, &tot);
+    T run = (T)part[blockIdx.x] + ex;
+    for (int j = 0; j < kScanItems; ++j) {
+        const int64_t e = first + j;
+        if (e < len) a[e] = run;
+        run += loc[j];
+    }
+}
+
+// The reduce step above sums a strided layout and the apply step a blocked
+// one; both cover exactly the tile [b * kScanTile, (b + 1) * kScanTile), so
+// the per-tile totals agree.
+template <typename T>
+static hipError_t exclusive_scan(T *a, int64_t len, unsigned long long *part, hipStream_t s)
+{
+    if (len <= 0) return hipSuccess;
+    const int64_t nblk = (len + kScanTile - 1) / kScanTile;
+    k_scan_reduce<T><<<(unsigned)nblk, kScanThreads, 0, s>>>(len, a, part);
+    k_scan_partials<<<1, kScanThreads, 0, s>>>(nblk, part);
+    k_scan_apply<T><<<(unsigned)nblk, kScanThreads, 0, s>>>(len, a, part);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// cell ranges
+
+__global__ void k_fill_u64(int64_t len, unsigned long long *__restrict__ a)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < len) a[i] = 0ull;
+}
+
+// Count keys, one atomic per run of equal keys inside a wave.
+__global__ void k_count_keys(int32_t n, const uint32_t *__restrict__ keys,
+                             unsigned long long *__restrict__ ks)
+{
+    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    const bool valid = i < n;
+    const uint32_t k = valid ? keys[i] : 0xffffffffu;
+    const uint32_t kprev = __shfl_up(k, 1);
+    const int lane = lane_id();
+    const bool head = valid && (lane == 0 || kprev != k);
+    const unsigned long long heads = ballot(head);
+    const unsigned long long vmask = ballot(valid);
+    if (head) {
+        // run length: up to the next head in this wave or the end of valid lanes
+        const unsigned long long after = lane == 63 ? 0ull : (heads >> (lane + 1)) << (lane + 1);
+        int end;
+        if (after) end = __ffsll((long long)after) - 1;
+        else end = 64 - __clzll((long long)vmask);
+        atomicAdd(&ks[k], ((unsigned long long)(end - lane)) << 32);
+    }
+}
+
+__global__ void k_mark_nonempty(int64_t nkeys, unsigned long long *__restrict__ ks)
+{
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < nkeys) {
+        const unsigned long long v = ks[k];
+        if (v) ks[k] = v | 1ull;
+    }
+}
+
+// After the exclusive scan, ks[k] = (first slot of key k) << 32 | (number of
+// non-empty keys before k).
+__global__ void k_emit_ranges(int64_t nkeys, int32_t n, int32_t ncell,
+                              const unsigned long long *__restrict__ ks,
+                              int32_t *__restrict__ start, int32_t *__restrict__ list,
+                              int32_t *__restrict__ info)
+{
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k > nkeys) return;
+    const unsigned long long v = ks[k];
+    const int32_t st = (int32_t)(v >> 32);
+    start[k] = st;
+    if (k == nkeys) {
+        // ks[nkeys] = totals: all particles, all non-empty keys
+        return;
+    }
+    const unsigned long long vn = ks[k + 1];
+    const int32_t cnt = (int32_t)(vn >> 32) - st;
+    const int32_t li = (int32_t)(v & 0xffffffffull);
+    if (cnt > 0 && k < 2 * (int64_t)ncell) list[li] = (int32_t)k;
+    if (k == ncell) info[0] = li;                          // boundary cells
+    if (k == 2 * (int64_t)ncell) {
+        info[1] = li - (int32_t)(ks[ncell] & 0xffffffffull);  // fluid cells
+        info[2] = n - st;                                   // excluded particles
+        info[3] = 0;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// gather into sorted order
+
+__global__ void k_gather(int32_t n, const uint32_t *__restrict__ perm,
+                         const int32_t *__restrict__ cell_in, const float4 *__restrict__ pos_in,
+                         const float4 *__restrict__ vr_in, const float4 *__restrict__ vp_in,
+                         const int32_t *__restrict__ id_in, int32_t *__restrict__ cell_out,
+                         float4 *__restrict__ pos_out, float4 *__restrict__ vr_out,
+                         float4 *__restrict__ vp_out, int32_t *__restrict__ id_out,
+                         int32_t *__restrict__ perm_out)
+{
+    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint32_t j = perm[i];
+    cell_out[i] = cell_in[j];
+    pos_out[i] = pos_in[j];
+    vr_out[i] = vr_in[j];
+    vp_out[i] = vp_in[j];
+    id_out[i] = id_in[j];
+    perm_out[i] = (int32_t)j;
+}
+
+hipError_t launch_build_cells(const sph_grid *g, const sph_state *src, sph_state *dst,
+                              sph_cells *cells, int32_t *perm, const Workspace &w,
+                              int32_t *dev_status, hipStream_t s)
+{
+    (void)dev_status;
+    const int32_t n = src->n;
+    const int32_t ncell = (int32_t)ncell_of(g);
+    const int64_t nkeys = 2 * (int64_t)ncell + 1;  // keys 0 .. 2 ncell
+    const int threads = 256;
+    dst->n = src->n;
+    dst->nb = src->nb;
+
+    // 1. keys
+    if (n > 0)
+        k_keys<<<(n + threads - 1) / threads, threads, 0, s>>>(n, src->nb, ncell, src->cell,
+                                                                  w.keys0, w.vals0);
+    // 2. radix sort over the bits of the largest key
+    int bits = 0;
+    while (bits < 32 && ((uint64_t)1 << bits) <= (uint64_t)(2 * (int64_t)ncell)) ++bits;
+    uint32_t *kin = w.keys0, *vin = w.vals0, *kout = w.keys1, *vout = w.vals1;
+    const int nblk = nblk_sort(n);
+    for (int shift = 0; shift < bits && n > 0; shift += kRadixBits) {
+        k_radix_hist<<<nblk, kSortThreads, 0, s>>>(n, shift, kin, w.hist, nblk);
+        hipError_t e = exclusive_scan<uint32_t>(w.hist, (int64_t)kRadix * nblk, w.partials, s);
+        if (e != hipSuccess) return e;
+        k_radix_scatter<<<nblk, kSortThreads, 0, s>>>(n, shift, kin, vin, kout, vout, w.hist, nblk);
+        uint32_t *t;
+        t = kin; kin = kout; kout = t;
+        t = vin; vin = vout; vout = t;
+    }
+    // 3. key counts -> packed (count, non-empty) -> exclusive scan -> ranges
+    const int64_t lenks = nkeys + 1;
+    k_fill_u64<<<(unsigned)((lenks + threads - 1) / threads), threads, 0, s>>>(lenks, w.keyscan);
+    if (n > 0) k_count_keys<<<(n + threads - 1) / threads, threads, 0, s>>>(n, kin, w.keyscan);
+    k_mark_nonempty<<<(unsigned)((nkeys + threads - 1) / threads), threads, 0, s>>>(nkeys,
+                                                                                   w.keyscan);
+    hipError_t e = exclusive_scan<unsigned long long>(w.keyscan, lenks, w.partials, s);
+    if (e != hipSuccess) return e;
+    k_emit_ranges<<<(unsigned)((lenks + threads - 1) / threads), threads, 0, s>>>(
+        nkeys, n, ncell, w.keyscan, cells->start, cells->list, cells->info);
+    // 4. gather
+    if (n > 0)
+        k_gather<<<(n + threads - 1) / threads, threads, 0, s>>>(
+            n, vin, src->cell, (const float4 *)src->pos, (const float4 *)src->velrho,
+            (const float4 *)src->velrho_prev, src->id, dst->cell, (float4 *)dst->pos,
+            (float4 *)dst->velrho, (float4 *)dst->velrho_prev, dst->id, perm);
+    return hipGetLastError();
+}
+
+}  // namespace sph

@@ -1,0 +1,149 @@
+// sph_internal.h -- shared declarations of the gfx950 kernels and host launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "sph.h"
+
+namespace sph {
+
+constexpr int kWave = 64;            // CDNA4 wavefront
+constexpr int kSortThreads = 256;    // radix sort block
+constexpr int kSortItems = 8;        // keys per thread per block
+constexpr int kSortTile = kSortThreads * kSortItems;
+constexpr int kRadixBits = 8;
+constexpr int kRadix = 1 << kRadixBits;
+constexpr int kScanThreads = 256;
+constexpr int kScanItems = 16;
+constexpr int kScanTile = kScanThreads * kScanItems;
+constexpr int kReduceThreads = 256;
+constexpr int kReduceBlocksMax = 1024;
+
+inline int64_t ncell_of(const sph_grid *g)
+{
+    return (int64_t)g->nc[0] * g->nc[1] * g->nc[2];
+}
+
+inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// Workspace layout, shared by every entry point of one simulation.
+struct Workspace {
+    uint32_t *keys0, *vals0, *keys1, *vals1;  // radix ping-pong [n] each
+    uint32_t *hist;                           // [kRadix * nblk_sort]
+    unsigned long long *partials;             // scan partial sums
+    unsigned long long *keyscan;              // [nkeys + 1] packed (count << 32 | nonempty)
+    int32_t *counters;                        // [16] work queues and flags
+    double *reduce;                           // [3 * kReduceBlocksMax] CFL partials
+    size_t bytes;
+};
+
+inline int nblk_sort(int64_t n) { return (int)((n + kSortTile - 1) / kSortTile); }
+
+inline size_t scan_partials_needed(int64_t len) { return (size_t)((len + kScanTile - 1) / kScanTile) + 1; }
+
+inline bool layout_workspace(const sph_grid *g, int64_t n, void *base, Workspace *w)
+{
+    const int64_t ncell = ncell_of(g);
+    const int64_t nkeys = 2 * ncell + 1;
+    const int64_t nb = nblk_sort(n);
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off += align256(bytes);
+        return o;
+    };
+    const size_t o_k0 = take(sizeof(uint32_t) * (size_t)(n > 0 ? n : 1));
+    const size_t o_v0 = take(sizeof(uint32_t) * (size_t)(n > 0 ? n : 1));
+    const size_t o_k1 = take(sizeof(uint32_t) * (size_t)(n > 0 ? n : 1));
+    const size_t o_v1 = take(sizeof(uint32_t) * (size_t)(n > 0 ? n : 1));
+    const size_t o_h = take(sizeof(uint32_t) * (size_t)kRadix * (size_t)(nb > 0 ? nb : 1));
+    size_t np = scan_partials_needed((int64_t)kRadix * nb);
+    const size_t np2 = scan_partials_needed(nkeys + 1);
+    if (np2 > np) np = np2;
+    const size_t o_p = take(sizeof(unsigned long long) * np);
+    const size_t o_ks = take(sizeof(unsigned long long) * (size_t)(nkeys + 1));
+    const size_t o_c = take(sizeof(int32_t) * 16);
+    const size_t o_r = take(sizeof(double) * 3 * kReduceBlocksMax);
+    w->bytes = off;
+    if (base) {
+        char *b = (char *)base;
+        w->keys0 = (uint32_t *)(b + o_k0);
+        w->vals0 = (uint32_t *)(b + o_v0);
+        w->keys1 = (uint32_t *)(b + o_k1);
+        w->vals1 = (uint32_t *)(b + o_v1);
+        w->hist = (uint32_t *)(b + o_h);
+        w->partials = (unsigned long long *)(b + o_p);
+        w->keyscan = (unsigned long long *)(b + o_ks);
+        w->counters = (int32_t *)(b + o_c);
+        w->reduce = (double *)(b + o_r);
+    }
+    return true;
+}
+
+// FP32 constants of the pair kernels, derived once on the host in FP64.
+struct PairConsts {
+    float cellf;     // cell side
+    float rc2;       // (2h)^2
+    float h;         // smoothing length
+    float inv_h;     // 1/h
+    float kf;        // F = kf (1 - q/2)^3, kf = -5 aD / h^2, aD = 21 / (16 pi h^3)
+    float eta2;
+    float alpha;
+    float c0;
+    float rho0;
+    float inv_rho0;
+    float gx, gy, gz;
+    float mass;
+    int32_t nsub;
+    int32_t nc0, nc1, nc2;
+    int32_t ncell;
+    int32_t n;       // particles in the state
+};
+
+// Host launchers (one per source file).
+hipError_t launch_encode(const sph_grid *g, const sph_params *p, const double *x, const double *v,
+                         const double *rho, sph_state *st, int32_t *dev_status, hipStream_t s);
+hipError_t launch_decode(const sph_grid *g, const sph_params *p, const sph_state *st, double *x,
+                         double *v, double *rho, hipStream_t s);
+hipError_t launch_build_cells(const sph_grid *g, const sph_state *src, sph_state *dst,
+                              sph_cells *cells, int32_t *perm, const Workspace &w,
+                              int32_t *dev_status, hipStream_t s);
+hipError_t launch_interact(const sph_grid *g, const sph_params *p, const sph_state *st,
+                           const sph_cells *cells, unsigned parts, float *ace, float *visc,
+                           unsigned long long *npairs, int32_t *nbr_stats, const Workspace &w,
+                           hipStream_t s);
+hipError_t launch_step(const sph_grid *g, const sph_params *p, sph_state *st, const float *ace,
+                       const float *visc, double *dt, long long step, unsigned flags,
+                       const Workspace &w, int32_t *dev_status, hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// Device helpers
+
+// Tait pressure over rho^2 for gamma = 7, FP64:  B ((1+d)^7 - 1) / rho^2 with
+// (1+d)^7 - 1 = d * sum_{k<7} (1+d)^k (no cancellation near rho0).
+__device__ inline double p_over_rho2(double w, double rho0, double B)
+{
+    const double d = w / rho0;
+    const double u = 1.0 + d;
+    double s = 1.0;
+    for (int k = 0; k < 6; ++k) s = fma(s, u, 1.0);
+    const double rho = rho0 + w;
+    return B * d * s / (rho * rho);
+}
+
+__device__ inline unsigned long long ballot(bool pred)
+{
+    return __builtin_amdgcn_ballot_w64(pred);
+}
+
+// number of set bits of m in lanes below this lane
+__device__ inline unsigned lane_rank(unsigned long long m)
+{
+    return __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32),
+                                     __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
+}
+
+__device__ inline int lane_id() { return (int)lane_rank(~0ull); }
+
+}  // namespace sph

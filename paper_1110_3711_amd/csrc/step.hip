@@ -1,0 +1,205 @@
+// step.hip -- system-update stage (Section 4.1 "SU"): the variable time step
+// from global maxima (FP64 block reduction, deterministic) and the Verlet
+// update (Table 1) with an FP64 position update that re-bins each particle
+// into (cell, FP32 offset).
+#include "sph_internal.h"
+
+namespace sph {
+
+struct StepConsts {
+    double org[3], hi[3];
+    double cell;
+    int32_t nc[3];
+    double h, rho0, c0, cfl, B;
+    int32_t verlet_ns, bound_floor;
+};
+
+// Per block: max |a|^2 and max (c + visc) over fluid, non-excluded slots, and
+// a flag for non-finite values.  out[3 b + {0,1,2}].
+__global__ __launch_bounds__(kReduceThreads) void k_cfl_partial(
+    StepConsts C, int32_t n, int32_t nb, const int32_t *__restrict__ cell,
+    const float4 *__restrict__ velrho, const float4 *__restrict__ ace,
+    const float *__restrict__ visc, double *__restrict__ out)
+{
+    __shared__ double s_a[kReduceThreads], s_c[kReduceThreads], s_f[kReduceThreads];
+    // Every value the update consumes is checked: a non-finite acceleration,
+    // density rate or viscosity anywhere (fluid or boundary) flags the step.
+    double am = 0.0, cm = 0.0, bad = 0.0;
+    const double big = 1.7976931348623157e308;
+    for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        if (cell[i] == SPH_EXCLUDED) continue;
+        const float4 a = ace[i];
+        if (i < nb) {
+            if (!(fabs((double)a.w) <= big)) bad = 1.0;
+            continue;
+        }
+        const double ax = a.x, ay = a.y, az = a.z;
+        const double a2 = ax * ax + ay * ay + az * az;
+        const double t = (C.rho0 + (double)velrho[i].w) / C.rho0;
+        const double cv = C.c0 * t * t * t + (double)visc[i];
+        if (!(a2 <= big) || !(cv <= big) || !(fabs((double)a.w) <= big)) bad = 1.0;
+        else {
+            am = fmax(am, a2);
+            cm = fmax(cm, cv);
+        }
+    }
+    const int t = threadIdx.x;
+    s_a[t] = am;
+    s_c[t] = cm;
+    s_f[t] = bad;
+    __syncthreads();
+    for (int o = kReduceThreads / 2; o > 0; o >>= 1) {
+        if (t < o) {
+            s_a[t] = fmax(s_a[t], s_a[t + o]);
+            s_c[t] = fmax(s_c[t], s_c[t + o]);
+            s_f[t] = fmax(s_f[t], s_f[t + o]);
+        }
+        __syncthreads();
+    }
+    if (t == 0) {
+        out[3 * blockIdx.x] = s_a[0];
+        out[3 * blockIdx.x + 1] = s_c[0];
+        out[3 * blockIdx.x + 2] = s_f[0];
+    }
+}
+
+// dt = cfl * min( sqrt(h / max|a|), h / max(c + visc) ); the minimum over
+// particles of a monotone function equals the function of the maximum.
+__global__ __launch_bounds__(kReduceThreads) void k_cfl_final(StepConsts C, int nblk,
+                                                             const double *__restrict__ part,
+                                                             double *__restrict__ dt,
+                                                             int32_t *__restrict__ dev_status)
+{
+    __shared__ double s_a[kReduceThreads], s_c[kReduceThreads], s_f[kReduceThreads];
+    const int t = threadIdx.x;
+    double am = 0.0, cm = 0.0, bad = 0.0;
+    for (int b = t; b < nblk; b += kReduceThreads) {
+        am = fmax(am, part[3 * b]);
+        cm = fmax(cm, part[3 * b + 1]);
+        bad = fmax(bad, part[3 * b + 2]);
+    }
+    s_a[t] = am;
+    s_c[t] = cm;
+    s_f[t] = bad;
+    __syncthreads();
+    for (int o = kReduceThreads / 2; o > 0; o >>= 1) {
+        if (t < o) {
+            s_a[t] = fmax(s_a[t], s_a[t + o]);
+            s_c[t] = fmax(s_c[t], s_c[t + o]);
+            s_f[t] = fmax(s_f[t], s_f[t + o]);
+        }
+        __syncthreads();
+    }
+    if (t == 0) {
+        const double inf = __builtin_inf();
+        const double tf = s_a[0] > 0.0 ? sqrt(C.h / sqrt(s_a[0])) : inf;
+        const double tc = s_c[0] > 0.0 ? C.h / s_c[0] : inf;
+        double d = C.cfl * fmin(tf, tc);
+        if (s_f[0] != 0.0 || !(d > 0.0) || !(d < inf)) {
+            atomicOr(dev_status, SPH_DEV_NONFINITE);
+            d = __builtin_nan("");
+        }
+        dt[0] = d;
+    }
+}
+
+__device__ inline void decode_cell(int32_t c, const int32_t *nc, int32_t &kx, int32_t &ky, int32_t &kz)
+{
+    kx = c % nc[0];
+    ky = (c / nc[0]) % nc[1];
+    kz = c / (nc[0] * nc[1]);
+}
+
+__global__ void k_verlet(StepConsts C, int32_t n, int32_t nb, int corrective,
+                         const double *__restrict__ dtp, int32_t *__restrict__ cell,
+                         float4 *__restrict__ pos, float4 *__restrict__ velrho,
+                         float4 *__restrict__ velrho_prev, const float4 *__restrict__ ace,
+                         int32_t *__restrict__ dev_status)
+{
+    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double dt = dtp[0];
+    if (!(dt > 0.0 && dt < __builtin_inf())) return;  // non-finite time step: state kept
+    const int32_t c = cell[i];
+    if (c == SPH_EXCLUDED) return;
+    const float4 a = ace[i];
+    const float4 vr = velrho[i];
+    const float4 vp = velrho_prev[i];
+    const double D = a.w;
+    double w1 = corrective ? (double)vr.w + dt * D : (double)vp.w + 2.0 * dt * D;
+    if (i < nb) {
+        if (C.bound_floor && w1 < 0.0) w1 = 0.0;
+        velrho_prev[i] = vr;
+        velrho[i] = make_float4(vr.x, vr.y, vr.z, (float)w1);
+        pos[i].w = (float)p_over_rho2(w1, C.rho0, C.B);
+        return;
+    }
+    int32_t k[3];
+    decode_cell(c, C.nc, k[0], k[1], k[2]);
+    const float of[3] = {pos[i].x, pos[i].y, pos[i].z};
+    const float vf[3] = {vr.x, vr.y, vr.z};
+    const float pf[3] = {vp.x, vp.y, vp.z};
+    const float af[3] = {a.x, a.y, a.z};
+    float on[3], vn[3];
+    bool out = false;
+    for (int d = 0; d < 3; ++d) {
+        const double u = (double)of[d] + dt * (double)vf[d] + 0.5 * dt * dt * (double)af[d];
+        const double sh = floor(u / C.cell + 0.5);
+        const int64_t kn = (int64_t)k[d] + (int64_t)sh;
+        on[d] = (float)fma(-sh, C.cell, u);
+        const double xabs = fma((double)kn + 0.5, C.cell, C.org[d]) + (double)on[d];
+        if (kn < 0 || kn >= C.nc[d] || !(xabs >= C.org[d] && xabs < C.hi[d])) out = true;
+        k[d] = (int32_t)kn;
+        vn[d] = (float)(corrective ? (double)vf[d] + dt * (double)af[d]
+                                   : (double)pf[d] + 2.0 * dt * (double)af[d]);
+    }
+    velrho_prev[i] = vr;
+    velrho[i] = make_float4(vn[0], vn[1], vn[2], (float)w1);
+    const float pw = (float)p_over_rho2(w1, C.rho0, C.B);
+    if (out) {
+        cell[i] = SPH_EXCLUDED;
+        pos[i] = make_float4(0.f, 0.f, 0.f, pw);
+        atomicOr(dev_status, SPH_DEV_OUT_OF_GRID);
+        return;
+    }
+    cell[i] = k[0] + C.nc[0] * (k[1] + C.nc[1] * k[2]);
+    pos[i] = make_float4(on[0], on[1], on[2], pw);
+}
+
+hipError_t launch_step(const sph_grid *g, const sph_params *p, sph_state *st, const float *ace,
+                       const float *visc, double *dt, long long step, unsigned flags,
+                       const Workspace &w, int32_t *dev_status, hipStream_t s)
+{
+    StepConsts C;
+    for (int d = 0; d < 3; ++d) {
+        C.org[d] = g->origin[d];
+        C.hi[d] = g->hi[d];
+        C.nc[d] = g->nc[d];
+    }
+    C.cell = g->cell;
+    C.h = p->h;
+    C.rho0 = p->rho0;
+    C.c0 = p->c0;
+    C.cfl = p->cfl;
+    C.B = p->c0 * p->c0 * p->rho0 / p->gamma;
+    C.verlet_ns = p->verlet_ns;
+    C.bound_floor = p->bound_floor;
+    const int32_t n = st->n, nb = st->nb;
+    if (!(flags & SPH_FIXED_DT)) {
+        int nblk = (int)(((int64_t)n + kReduceThreads - 1) / kReduceThreads);
+        if (nblk > kReduceBlocksMax) nblk = kReduceBlocksMax;
+        if (nblk < 1) nblk = 1;
+        k_cfl_partial<<<nblk, kReduceThreads, 0, s>>>(C, n, nb, st->cell, (const float4 *)st->velrho,
+                                                      (const float4 *)ace, visc, w.reduce);
+        k_cfl_final<<<1, kReduceThreads, 0, s>>>(C, nblk, w.reduce, dt, dev_status);
+    }
+    const int corrective = step == 0 || ((step + 1) % p->verlet_ns) == 0;
+    if (n > 0)
+        k_verlet<<<(n + 255) / 256, 256, 0, s>>>(C, n, nb, corrective, dt, st->cell,
+                                                 (float4 *)st->pos, (float4 *)st->velrho,
+                                                 (float4 *)st->velrho_prev, (const float4 *)ace,
+                                                 dev_status);
+    return hipGetLastError();
+}
+
+}  // namespace sph

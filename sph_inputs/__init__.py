@@ -8,6 +8,7 @@ of the method's code.
 """
 
 from .dambreak import (  # noqa: F401
+    CASES,
     SEED_BASE,
     Case,
     Layout,

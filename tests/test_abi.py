@@ -1,0 +1,119 @@
+"""The C ABI library loads and exports every symbol declared in include/sph.h;
+host-side validation rejects bad arguments before touching the device.  No
+compute call is made (runs without a GPU)."""
+
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "sph.h")).read()
+    return sorted(set(re.findall(r"SPH_API\s+[\w\s\*]+?\b(sph_\w+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_1110_3711_amd import sph
+
+    if not os.path.exists(sph.LIB_PATH):
+        pytest.fail("libsph.so is not built (run __graft_entry__.build())")
+    return sph.load()
+
+
+def test_header_declares_the_four_calls():
+    names = _declared()
+    for f in ["sph_build_cells", "sph_interact", "sph_step", "sph_interact_backward"]:
+        assert f in names
+
+
+def test_library_exports_every_declared_symbol(lib):
+    from paper_1110_3711_amd import sph
+
+    for name in _declared():
+        assert hasattr(lib, name), name
+    assert sorted(sph.EXPORTS) == _declared()
+    assert lib.sph_abi_version() == 1
+
+
+def _grid():
+    from paper_1110_3711_amd import sph
+
+    return sph.make_grid([0, 0, 0], [1, 1, 1], 0.05, [20, 20, 20], 1)
+
+
+def test_workspace_query(lib):
+    from paper_1110_3711_amd import sph
+
+    g = _grid()
+    assert sph.sph_workspace_bytes(g, 1000) > 16 * 1000
+    assert sph.sph_workspace_bytes(g, 0) > 0
+    bad = sph.make_grid([0, 0, 0], [1, 1, 1], 0.05, [20, 20, 20], 3)
+    assert sph.sph_workspace_bytes(bad, 1000) == 0
+    small = sph.make_grid([0, 0, 0], [1, 1, 1], 0.01, [20, 20, 20], 1)  # does not cover
+    assert sph.sph_workspace_bytes(small, 1000) == 0
+    assert sph.sph_workspace_bytes(g, -1) == 0
+
+
+def test_validation_errors_before_any_device_work(lib):
+    from paper_1110_3711_amd import sph
+    from sph_inputs import physics
+
+    g = _grid()
+    p = sph.make_params(physics(0.01))  # 2h = 0.0416 < cell 0.05 -> ok
+    st = sph.State()
+    st.n, st.nb = 10, 11  # nb > n
+    cells = sph.Cells()
+    assert lib.sph_build_cells(C.byref(g), C.byref(st), C.byref(st), C.byref(cells), None, None,
+                               0, None, None) == sph.SPH_ERR_ARG
+    assert lib.sph_interact(None, C.byref(p), C.byref(st), C.byref(cells), 3, None, None, None,
+                            None, None, 0, None) == sph.SPH_ERR_ARG
+    st.nb = 0
+    # non-null fake pointers: validation must still stop at the workspace size
+    fake = C.c_void_p(16)
+    st.cell = st.pos = st.velrho = st.velrho_prev = st.id = 16
+    st2 = sph.State()
+    st2.n, st2.nb = 10, 0
+    st2.cell = st2.pos = st2.velrho = st2.velrho_prev = st2.id = 32
+    cells.start = cells.list = cells.info = 16
+    assert lib.sph_build_cells(C.byref(g), C.byref(st), C.byref(st2), C.byref(cells), fake, fake, 8,
+                               fake, None) == sph.SPH_ERR_WORKSPACE
+    # src and dst may not alias
+    assert lib.sph_build_cells(C.byref(g), C.byref(st), C.byref(st), C.byref(cells), fake, fake,
+                               1 << 40, fake, None) == sph.SPH_ERR_ARG
+    # stencil smaller than the support: cell * nsub < 2h
+    p2 = sph.make_params(physics(0.02))  # 2h = 0.083 > 0.05
+    assert lib.sph_interact(C.byref(g), C.byref(p2), C.byref(st), C.byref(cells), 3, fake, fake,
+                            None, None, fake, 1 << 40, None) == sph.SPH_ERR_ARG
+    # unknown parts selector
+    assert lib.sph_interact(C.byref(g), C.byref(p), C.byref(st), C.byref(cells), 4, fake, fake,
+                            None, None, fake, 1 << 40, None) == sph.SPH_ERR_ARG
+    # gamma other than 7 and unknown kernels are rejected
+    p3 = sph.make_params(physics(0.01))
+    p3.gamma = 5.0
+    assert lib.sph_interact(C.byref(g), C.byref(p3), C.byref(st), C.byref(cells), 3, fake, fake,
+                            None, None, fake, 1 << 40, None) == sph.SPH_ERR_ARG
+    p4 = sph.make_params(physics(0.01))
+    p4.kernel = 7
+    assert lib.sph_step(C.byref(g), C.byref(p4), C.byref(st), fake, fake, fake, 0, 0, None, fake,
+                        1 << 40, fake, None) == sph.SPH_ERR_ARG
+    # unknown flags, negative step
+    assert lib.sph_step(C.byref(g), C.byref(p), C.byref(st), fake, fake, fake, 0, 64, None, fake,
+                        1 << 40, fake, None) == sph.SPH_ERR_ARG
+    assert lib.sph_step(C.byref(g), C.byref(p), C.byref(st), fake, fake, fake, -1, 0, None, fake,
+                        1 << 40, fake, None) == sph.SPH_ERR_ARG
+
+
+def test_product_path_has_no_cpu_fallback():
+    # the package must not import the oracle anywhere
+    pkg = os.path.join(ROOT, "paper_1110_3711_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".h", ".cpp")):
+                txt = open(os.path.join(dirpath, f)).read()
+                assert "import oracle" not in txt and "from oracle" not in txt, f
+                assert "sph_oracle" not in txt, f

@@ -1,0 +1,189 @@
+"""sph_step on the GPU against the oracle's time step and Verlet update, from
+the same encoded state; per-step force parity along an oracle trajectory; the
+device-side failure paths (leaving the domain, non-finite time step)."""
+
+import numpy as np
+import pytest
+
+from _helpers import grid_tuple, oracle_view, rel_l2
+from sph_inputs import dam_break, named_case, physics
+from sph_inputs.dambreak import Layout
+
+pytestmark = pytest.mark.gpu
+
+
+def _oracle_state(ora, lay, sim, vprev=None, rhoprev=None):
+    gt = grid_tuple(sim)
+    xq, vq, rq, excl, _, _ = oracle_view(ora, lay.x, lay.v, lay.rho, lay.phys.rho0, gt, lay.lo,
+                                         lay.hi)
+    S = ora.State(lay)
+    S.x[:], S.v[:], S.rho[:], S.excl[:] = xq, vq, rq, excl
+    if vprev is not None:
+        S.vprev[:] = np.asarray(vprev).astype(np.float32).astype(np.float64)
+        S.rhoprev[:] = (np.asarray(rhoprev) - lay.phys.rho0).astype(np.float32).astype(
+            np.float64) + lay.phys.rho0
+    else:
+        S.vprev[:], S.rhoprev[:] = vq, rq
+    return S
+
+
+@pytest.mark.parametrize("step_index", [0, 5])
+def test_one_step_matches_oracle(ora, step_index):
+    import torch
+
+    from paper_1110_3711_amd import sph
+
+    lay = dam_break(0.01, 11103712, vel_sigma=0.1, vel_seed=3)
+    rng = np.random.default_rng(9)
+    vprev = lay.v + rng.normal(0, 0.01, lay.v.shape)
+    vprev[: lay.nb] = 0
+    rhoprev = lay.rho + rng.normal(0, 0.05, lay.n)
+    print(f"step parity step={step_index}", flush=True)
+    sim = sph.Simulation(lay, nsub=1)
+    sim.upload_prev(vprev, rhoprev)
+    sim.step_index = step_index
+    sim.step()
+    torch.cuda.synchronize()
+    assert sim.dev_status() == 0
+    x, v, r = sim.decode()
+    S = _oracle_state(ora, lay, sim, vprev, rhoprev)
+    S.step = step_index
+    ace, visc, _, _ = S.interact()
+    dt = ora.time_step(S.rho, ace, visc, S.nb, S.P, S.excl)
+    S.verlet(ace, dt)
+    assert sim.dt.item() == pytest.approx(dt, rel=1e-5)
+    f = slice(lay.nb, None)
+    cell = sim.grid.cell
+    # positions: FP32 offset storage (half an ulp of cell/2) plus the FP32
+    # acceleration error times dt^2/2 and the dt error times |v|
+    tol_x = np.spacing(np.float32(cell / 2)) + 1e-5 * dt * (np.abs(S.v[f]).max() + 1)
+    assert np.abs(x[f] - S.x[f]).max() <= tol_x
+    assert np.array_equal(x[: lay.nb], S.x[: lay.nb])
+    assert rel_l2(v[f], S.v[f]) <= 1e-5
+    dr_gpu = r - lay.rho
+    dr_ora = S.rho - lay.rho
+    assert rel_l2(dr_gpu, dr_ora) <= 1e-3  # density change (stored as FP32 rho - rho0)
+    assert np.all(r[: lay.nb] >= lay.phys.rho0)
+
+
+def test_per_step_force_parity_along_trajectory(ora):
+    """The oracle integrates cfg1 in FP64 for 100 steps; at every 10th step its
+    state is encoded on the device and the GPU forces are compared (1e-4)."""
+    import torch
+
+    from paper_1110_3711_amd import sph
+
+    lay = named_case("cfg1")
+    S = ora.State(lay)
+    errs = []
+    for k in range(11):
+        if k:
+            S.run(10)
+        snap = lay.copy()
+        snap.x, snap.v, snap.rho = S.x.copy(), S.v.copy(), S.rho.copy()
+        print(f"trajectory step {S.step}", flush=True)
+        sim = sph.Simulation(snap, nsub=1)
+        sim.build_cells()
+        sim.interact()
+        torch.cuda.synchronize()
+        gt = grid_tuple(sim)
+        xq, vq, rq, excl, _, _ = oracle_view(ora, snap.x, snap.v, snap.rho, lay.phys.rho0, gt,
+                                             lay.lo, lay.hi)
+        ref, rvisc, _, _ = ora.interact(xq, vq, rq, lay.nb, S.P, excl=excl)
+        ace = sim.by_id(sim.ace)
+        f = np.arange(lay.nb, lay.n)
+        e = rel_l2(ace[f, :3], ref[f, :3])
+        ed = rel_l2(ace[:, 3], ref[:, 3])
+        errs.append((S.step, e, ed))
+        assert e <= 1e-4 and ed <= 1e-4, errs[-1]
+    print("  per-step (step, acc, drho) rel L2:", errs)
+
+
+def _free(nf=3, hi_z=0.9):
+    ph = physics(0.01)
+    rng = np.random.default_rng(7)
+    x = np.array([[0.1, 0.1, 0.5], [0.5, 0.1, 0.5], [0.8, 0.1, 0.5]])[:nf]
+    v = rng.normal(0, 0.5, size=(nf, 3))
+    return Layout("free", x, v, np.full(nf, 1000.0), 0, ph, np.array([-0.2] * 3),
+                  np.array([1.0, 1.0, hi_z]))
+
+
+def test_free_fall_gpu(ora):
+    import torch
+
+    from paper_1110_3711_amd import sph
+
+    lay = _free()
+    print("free fall", flush=True)
+    sim = sph.Simulation(lay, nsub=1)
+    sim.run(97)
+    torch.cuda.synchronize()
+    x, v, _ = sim.decode()
+    h = lay.phys.h
+    dt = 0.2 * min(np.sqrt(h / 9.81), h / lay.phys.c0)
+    assert sim.dt.item() == pytest.approx(dt, rel=1e-6)
+    t = 97 * dt
+    g = np.array([0, 0, -9.81])
+    xv = np.asarray(lay.v).astype(np.float32).astype(np.float64)
+    assert np.allclose(v, xv + g * t, rtol=0, atol=1e-5)
+    assert np.allclose(x, lay.x + xv * t + 0.5 * g * t * t, rtol=0, atol=1e-6)
+
+
+def test_leaving_the_domain_sets_status_and_excludes(ora):
+    import torch
+
+    from paper_1110_3711_amd import sph
+
+    lay = _free(hi_z=0.5003)
+    lay.v[0] = [0, 0, 5.0]
+    lay.v[1:, 2] = 0.0  # the others fall
+    print("exclusion", flush=True)
+    sim = sph.Simulation(lay, nsub=1)
+    sim.run(3)
+    torch.cuda.synchronize()
+    assert sim.dev_status() & sph.SPH_DEV_OUT_OF_GRID
+    x, _, _ = sim.decode()
+    assert np.isnan(x[0]).all() and np.isfinite(x[1:]).all()
+    assert int(sim.info[2].item()) == 1
+    sim.run(2)  # excluded particles stay out, never interact
+    torch.cuda.synchronize()
+    assert int(sim.info[2].item()) == 1
+
+
+def test_nonfinite_time_step_keeps_state(ora):
+    import torch
+
+    from paper_1110_3711_amd import sph
+
+    lay = dam_break(0.02, 3, fluid=(0.1, 0.1, 0.1), tank=(0.2, 0.12, 0.12))
+    lay.v[lay.nb + 7] = [np.nan, 0.0, 0.0]
+    print("nonfinite", flush=True)
+    sim = sph.Simulation(lay, nsub=1)
+    sim.build_cells()
+    before = [t.clone() for t in (sim.a.cell, sim.a.pos, sim.a.velrho, sim.a.velrho_prev)]
+    sim.interact()
+    sim.update()
+    torch.cuda.synchronize()
+    assert sim.dev_status() & sph.SPH_DEV_NONFINITE
+    assert np.isnan(sim.dt.item())
+    after = (sim.a.cell, sim.a.pos, sim.a.velrho, sim.a.velrho_prev)
+    for b, a in zip(before, after):
+        assert torch.equal(torch.nan_to_num(b), torch.nan_to_num(a))
+
+
+def test_boundaries_fixed_and_floored(ora):
+    import torch
+
+    from paper_1110_3711_amd import sph
+
+    lay = named_case("cfg1")
+    print("boundary floor", flush=True)
+    sim = sph.Simulation(lay, nsub=1)
+    sim.run(20)
+    torch.cuda.synchronize()
+    x, v, r = sim.decode()
+    gt = grid_tuple(sim)
+    xq, *_ = oracle_view(ora, lay.x, lay.v, lay.rho, lay.phys.rho0, gt, lay.lo, lay.hi)
+    assert np.array_equal(x[: lay.nb], xq[: lay.nb])
+    assert np.all(v[: lay.nb] == 0)
+    assert np.all(r[: lay.nb] >= lay.phys.rho0) and np.any(r[: lay.nb] > lay.phys.rho0)
