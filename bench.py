@@ -84,6 +84,38 @@ def cpu_baseline(layout, budget_s: float = 12.0):
     }
 
 
+def adjoint_ratio(layout, steps: int, every: int):
+    """Wall time of the checkpointed backward pass (recompute + adjoint) over
+    the forward pass of the same rollout (both on the device, synchronised)."""
+    import torch
+
+    from paper_1110_3711_amd.rollout import Rollout
+
+    roll = Rollout(layout, steps, every)
+    v0 = torch.as_tensor(layout.v[layout.nb:], dtype=torch.float64, device=roll.device)
+    rng = np.random.default_rng(7)
+    target = torch.as_tensor(layout.x[layout.nb:].mean(0) + rng.uniform(-0.01, 0.01, 3),
+                             device=roll.device)
+    # untimed warm-up of every kernel on a short rollout
+    warm = Rollout(layout, every, every)
+    xw = warm.forward(layout.phys.alpha, v0)
+    warm.backward(torch.ones_like(xw))
+    del warm
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    xk = roll.forward(layout.phys.alpha, v0)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    gx = 2.0 / 3.0 * (xk.mean(0) - target) / xk.shape[0]
+    ga, gv = roll.backward(gx.expand_as(xk).contiguous())
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    ok = bool(torch.isfinite(gv).all().item()) and bool(torch.isfinite(ga).item())
+    return {"ratio": (t2 - t1) / (t1 - t0), "forward_s": t1 - t0, "backward_s": t2 - t1,
+            "steps": steps, "checkpoint_every": every, "finite": ok,
+            "alpha_grad": float(ga.item())}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -93,6 +125,11 @@ def main():
     ap.add_argument("--nsub", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=12.0)
+    ap.add_argument("--adjoint-steps", type=int, default=50)
+    ap.add_argument("--adjoint-every", type=int, default=10)
+    ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="run one 256 MiB device-to-device copy first (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); the "
@@ -104,6 +141,13 @@ def main():
     from paper_1110_3711_amd import sph
     from sph_inputs import CASES, named_case
 
+    if args.calibrate_copy:
+        a = torch.empty(64 << 20, dtype=torch.float32, device="cuda:0").fill_(1.0)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
     lay = named_case(args.config)
     sim = sph.Simulation(lay, nsub=args.nsub)
     stream = torch.cuda.current_stream()
@@ -190,10 +234,15 @@ def main():
         "pairs_per_step": pairs / K,
         "wall_s": wall,
         "adjoint_forward_ratio": None,
+        "adjoint": None,
         "dev_status": status,
         "paper_context": PAPER_CONTEXT,
         "roofline": roof,
     }
+    if not args.no_adjoint:
+        adj = adjoint_ratio(lay, args.adjoint_steps, args.adjoint_every)
+        out["adjoint"] = adj
+        out["adjoint_forward_ratio"] = adj["ratio"]
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(lay, args.cpu_budget)
     print(json.dumps(out), flush=True)

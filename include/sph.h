@@ -15,6 +15,8 @@
  *                          Verlet update (Section 4.1, Table 1).
  *   sph_interact_backward  vector-Jacobian product of sph_interact (no
  *                          counterpart in the paper).
+ *   sph_step(SPH_ADJOINT)  transpose of the Verlet update;
+ *   sph_build_cells_backward  transpose of the reorder of sph_build_cells.
  *   sph_encode/sph_decode  FP64 <-> device state conversion.
  *
  * Conventions shared by every entry point
@@ -121,12 +123,14 @@ typedef struct {
                        excluded particles, reserved                                     */
 } sph_cells;
 
-/* Adjoint buffers of one Verlet step (device, [4n] each, sorted slot order). */
+/* Adjoint buffers (device, [4n] each, in the slot order of one state).  The
+ * time step and the neighbour sets are held fixed; the Monaghan switch
+ * (v.r < 0) and the boundary density floor act as masks. */
 typedef struct {
-    float *pos_bar;         /* in: adjoint of x^{n+1} (xyz; w unused); out: of x^n       */
-    float *velrho_bar;      /* in: adjoint of (v, rho)^{n+1};   out: of (v, rho)^n      */
-    float *velrho_prev_bar; /* in: adjoint of the stored level-n copy; out: of level n-1 */
-    float *ace_bar;         /* out: adjoint of (a, drho/dt)^n                             */
+    float *pos_bar;         /* adjoint of x (xyz; w unused); boundary slots unused        */
+    float *velrho_bar;      /* adjoint of (v, rho) of the current level                   */
+    float *velrho_prev_bar; /* adjoint of (v, rho) stored as the previous level           */
+    float *ace_bar;         /* adjoint of (a, drho/dt) of one step (written by sph_step)  */
 } sph_adjoint;
 
 /* Size in bytes of the workspace needed by all calls for n particles on
@@ -196,17 +200,46 @@ SPH_API sph_status sph_interact(const sph_grid *g, const sph_params *p, const sp
  * floored at rho0 if bound_floor.  Unless SPH_FIXED_DT, a non-finite value
  * in ace or visc (any slot) or a non-finite time step sets SPH_DEV_NONFINITE,
  * writes NaN to dt[0] and leaves the state unchanged.
- * Adjoint mode: see sph_adjoint (not built yet: returns SPH_ERR_ARG). */
+ * Adjoint mode (flags SPH_ADJOINT, adj != NULL): st, ace and dt[0] are the
+ * state, (a, D) and time step of the forward step being transposed (st before
+ * its update).  In: adj->pos_bar, velrho_bar, velrho_prev_bar = adjoints of
+ * level n+1.  Out: adj->ace_bar = adjoint of (a, D)^n:
+ *   regular:    abar = dt^2/2 xbar' + 2 dt vbar',  Dbar = 2 dt rhobar',
+ *   corrective: abar = dt^2/2 xbar' + dt vbar',    Dbar = dt rhobar',
+ * and the three adjoint arrays replaced by those of level n (through the
+ * update only; add the interaction's VJP with sph_interact_backward):
+ *   xbar = xbar',  vbar = dt xbar' + vprevbar' (+ vbar' if corrective),
+ *   rhobar = rhoprevbar' (+ rhobar' if corrective),
+ *   (vprevbar, rhoprevbar) = regular ? (vbar', rhobar') : 0.
+ * Boundary slots: only the density entries; excluded slots unchanged. */
 SPH_API sph_status sph_step(const sph_grid *g, const sph_params *p, sph_state *st, const float *ace,
                     const float *visc, double *dt, long long step, unsigned flags,
                     sph_adjoint *adj, void *ws, size_t ws_bytes, int32_t *dev_status,
                     hipStream_t stream);
 
-/* VJP of sph_interact at state st (not built yet: returns SPH_ERR_ARG). */
+/* VJP of sph_interact at state st with the cells of the same build:
+ * ace_bar [4n] = (abar, Dbar) per slot (abar of boundary slots is ignored).
+ * Accumulates (+=), each slot written by exactly one thread:
+ *   pos_bar[i].xyz    += (d(a, D)/dx_i)^T ace_bar      (fluid slots)
+ *   velrho_bar[i].xyz += (d(a, D)/dv_i)^T ace_bar      (fluid slots)
+ *   velrho_bar[i].w   += (d(a, D)/drho_i)^T ace_bar    (all slots)
+ *   alpha_bar[0]      += (d a/d alpha)^T abar          (FP64, fixed-order sum)
+ * Gather form: for each particle, over its neighbours b, the derivative of the
+ * pair term (abar_a - abar_b) . T_ab + (Dbar_a + Dbar_b) S_ab, where
+ * T_ab = -m (P_a/rho_a^2 + P_b/rho_b^2 + Pi_ab) F_ab r_ab and
+ * S_ab = m (v_ab . r_ab) F_ab are the momentum and continuity pair terms. */
 SPH_API sph_status sph_interact_backward(const sph_grid *g, const sph_params *p, const sph_state *st,
                                  const sph_cells *cells, const float *ace_bar, float *pos_bar,
                                  float *velrho_bar, double *alpha_bar, void *ws,
                                  size_t ws_bytes, hipStream_t stream);
+
+/* Transpose of the reorder of sph_build_cells: src_bar[perm[i]] = dst_bar[i]
+ * for pos_bar, velrho_bar and velrho_prev_bar (ace_bar is not used).  perm
+ * is the array that sph_build_cells wrote; the two adjoint sets must not
+ * share arrays. */
+SPH_API sph_status sph_build_cells_backward(const int32_t *perm, int32_t n,
+                                            const sph_adjoint *dst_bar, sph_adjoint *src_bar,
+                                            hipStream_t stream);
 
 #ifdef __cplusplus
 }

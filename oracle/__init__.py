@@ -84,6 +84,13 @@ def lib():
         L.ora_decode.restype = None
         L.ora_count_f32.argtypes = [C.c_int, C.c_int, ip, fp, ip, C.c_float, C.c_float, ip, u32p]
         L.ora_count_f32.restype = C.c_longlong
+        L.ora_fprime.argtypes = [pp, C.c_double]
+        L.ora_fprime.restype = C.c_double
+        L.ora_interact_vjp.argtypes = [C.c_int, C.c_int, dp, dp, dp, u8p, pp, dp, dp, dp, dp, dp]
+        L.ora_interact_vjp.restype = None
+        L.ora_verlet_vjp.argtypes = [C.c_int, C.c_int, dp, dp, dp, C.c_double, C.c_longlong, u8p,
+                                     pp, dp, dp, dp, dp, dp, dp]
+        L.ora_verlet_vjp.restype = None
         L.ora_num_threads.argtypes = []
         L.ora_num_threads.restype = C.c_int
         _lib = L
@@ -122,6 +129,10 @@ def kernel_w(P, r):
 
 def kernel_f(P, r):
     return lib().ora_f(C.byref(P), float(r))
+
+
+def kernel_fprime(P, r):
+    return lib().ora_fprime(C.byref(P), float(r))
 
 
 def pressure(P, rho):
@@ -268,6 +279,85 @@ def count_f32(cidx, off, nb, nc, cellf, rc2f):
     tot = lib().ora_count_f32(n, nb, _p(cidx, C.c_int32), _p(off, C.c_float), _p(ncv, C.c_int32),
                               float(cellf), float(rc2f), _p(cnt, C.c_int32), _p(hs, C.c_uint32))
     return cnt, hs, tot
+
+
+def interact_vjp(x, v, rho, nb, P, abar, excl=None):
+    """(xbar[n,3], vbar[n,3], rhobar[n], alphabar) = J^T abar for abar[n,4]."""
+    x = _f64(x, (-1, 3))
+    v = _f64(v, (-1, 3))
+    rho = _f64(rho)
+    n = x.shape[0]
+    if excl is None:
+        excl = np.zeros(n, dtype=np.uint8)
+    excl = np.ascontiguousarray(excl, dtype=np.uint8)
+    abar = _f64(abar, (-1, 4))
+    xb = np.zeros((n, 3))
+    vb = np.zeros((n, 3))
+    rb = np.zeros(n)
+    al = np.zeros(1)
+    lib().ora_interact_vjp(n, nb, _p(x, C.c_double), _p(v, C.c_double), _p(rho, C.c_double),
+                           _p(excl, C.c_uint8), C.byref(P), _p(abar, C.c_double),
+                           _p(xb, C.c_double), _p(vb, C.c_double), _p(rb, C.c_double),
+                           _p(al, C.c_double))
+    return xb, vb, rb, float(al[0])
+
+
+def verlet_vjp(rho, rhoprev, ace, dt, step, nb, P, excl, xb, vb, rb, vpb, rpb):
+    """Transpose of one Verlet step (in place on the adjoint arrays); returns
+    abar[n,4], the adjoint of (A, D) of that step."""
+    rho = _f64(rho)
+    n = rho.size
+    rhoprev = _f64(rhoprev)
+    ace = _f64(ace, (-1, 4))
+    excl = np.ascontiguousarray(excl, dtype=np.uint8)
+    for a in (xb, vb, rb, vpb, rpb):
+        assert a.dtype == np.float64 and a.flags.c_contiguous
+    abar = np.zeros((n, 4))
+    lib().ora_verlet_vjp(n, nb, _p(rho, C.c_double), _p(rhoprev, C.c_double),
+                         _p(ace, C.c_double), float(dt), int(step), _p(excl, C.c_uint8),
+                         C.byref(P), _p(xb, C.c_double), _p(vb, C.c_double), _p(rb, C.c_double),
+                         _p(vpb, C.c_double), _p(rpb, C.c_double), _p(abar, C.c_double))
+    return abar
+
+
+def rollout(layout, dts, P=None, v0=None, step0=0):
+    """FP64 forward rollout with a given time-step sequence; returns the list
+    of per-step records (state before the step, its (A, D)) and the final
+    State.  Used by the adjoint checks (the time step is frozen)."""
+    S = State(layout, P)
+    if v0 is not None:
+        S.v[:] = v0
+        S.vprev[:] = v0
+    S.step = step0
+    tape = []
+    for dt in dts:
+        ace, visc, _, _ = S.interact()
+        tape.append((S.x.copy(), S.v.copy(), S.rho.copy(), S.rhoprev.copy(), S.excl.copy(),
+                     ace, S.step))
+        S.verlet(ace, dt)
+    return tape, S
+
+
+def rollout_vjp(layout, tape, dts, P, xbar_final):
+    """Reverse pass over a tape from ``rollout``: adjoint of the final
+    positions -> (vbar0 [n,3] of the initial velocity, alphabar)."""
+    n = layout.n
+    xb = np.ascontiguousarray(xbar_final, dtype=np.float64).copy()
+    vb = np.zeros((n, 3))
+    rb = np.zeros(n)
+    vpb = np.zeros((n, 3))
+    rpb = np.zeros(n)
+    alpha = 0.0
+    for (x, v, rho, rhoprev, excl, ace, step), dt in zip(reversed(tape), reversed(dts)):
+        abar = verlet_vjp(rho, rhoprev, ace, dt, step, layout.nb, P, excl, xb, vb, rb, vpb, rpb)
+        gx, gv, gr, ga = interact_vjp(x, v, rho, layout.nb, P, abar, excl)
+        f = slice(layout.nb, None)
+        xb[f] += gx[f]
+        vb[f] += gv[f]
+        rb += gr
+        alpha += ga
+    # v^{-1} = v^0 at the start: both levels are the initial velocity
+    return vb + vpb, alpha
 
 
 def num_threads():

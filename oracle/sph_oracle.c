@@ -544,6 +544,168 @@ ORA_EXPORT long long ora_count_f32(int n, int nb, const int32_t *cellidx, const 
     return total;
 }
 
+/* ------------------------------------------------------------------------ */
+/* Derivative of the kernel gradient factor: dF/dr.  Pinned by: finite
+ * differences of ora_f.                                                       */
+ORA_EXPORT double ora_fprime(const ora_params *p, double r)
+{
+    const double h = p->h, q = r / h;
+    if (q >= 2.0) return 0.0;
+    if (p->kernel == 0) {
+        const double ad = 21.0 / (16.0 * ORA_PI * h * h * h);
+        const double t = 1.0 - 0.5 * q;
+        return 15.0 * ad * t * t / (2.0 * h * h * h);
+    }
+    const double ad = 1.0 / (ORA_PI * h * h * h);
+    if (q < 1.0) return 2.25 * ad / (h * h * h);
+    if (r == 0.0) return 0.0;
+    return 0.75 * ad * (4.0 - q * q) / (h * h * h * q * q);
+}
+
+/* Vector-Jacobian product of ora_interact (no counterpart in the paper).
+ * Given abar[4 id + 0..2] = adjoint of the acceleration of a fluid particle
+ * and abar[4 id + 3] = adjoint of its density rate (any particle), add
+ *   xbar += (d(A, D)/dx)^T abar,  vbar += (d/dv)^T abar,
+ *   rhobar += (d/drho)^T abar,     alphabar += (d/dalpha)^T abar
+ * for the same neighbour sets as the forward (cell list, ascending ids).
+ * Written as the plain chain rule over every directed pair (a target, b
+ * neighbour), scattered to both particles; sequential.  The visc output and
+ * the time step are not differentiated; the Monaghan switch (v.r < 0) and
+ * the neighbour sets are held fixed.  Pinned by: central finite differences
+ * of ora_interact along random directions.                                  */
+ORA_EXPORT void ora_interact_vjp(int n, int nb, const double *x, const double *v,
+                                 const double *rho, const uint8_t *excl, const ora_params *p,
+                                 const double *abar, double *xbar, double *vbar, double *rhobar,
+                                 double *alphabar)
+{
+    const double rc2 = 4.0 * p->h * p->h, m = p->mass, h = p->h;
+    cell_list cl;
+    memset(&cl, 0, sizeof cl);
+    cells_build(&cl, n, excl, x, 2.0 * p->h);
+    int *buf = (int *)malloc(sizeof(int) * (size_t)(27 * cl.maxocc + 1));
+    double ab = 0.0;
+    for (int a = 0; a < n; ++a) {
+        if (excl[a]) continue;
+        const int cnt = nbr_cells(a, nb, excl, x, rc2, &cl, buf);
+        const int fluid_a = a >= nb;
+        const double Dbar = abar[4 * (size_t)a + 3];
+        const double Ab[3] = {abar[4 * (size_t)a], abar[4 * (size_t)a + 1], abar[4 * (size_t)a + 2]};
+        const double ra = rho[a];
+        const double Pa = ora_pressure(p, ra), ca = ora_sound(p, ra);
+        const double pa = Pa / (ra * ra);
+        const double dpa = ca * ca / (ra * ra) - 2.0 * Pa / (ra * ra * ra); /* d(P/rho^2)/drho */
+        const double dca = 0.5 * (p->gamma - 1.0) * ca / ra;                /* dc/drho */
+        for (int k = 0; k < cnt; ++k) {
+            const int b = buf[k];
+            double r[3], vv[3];
+            for (int d = 0; d < 3; ++d) {
+                r[d] = x[3 * a + d] - x[3 * b + d];
+                vv[d] = v[3 * a + d] - v[3 * b + d];
+            }
+            const double r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
+            const double rr = sqrt(r2);
+            const double F = ora_f(p, rr);
+            const double Fr = rr > 0.0 ? ora_fprime(p, rr) / rr : 0.0; /* dF/dr / r */
+            const double vdr = vv[0] * r[0] + vv[1] * r[1] + vv[2] * r[2];
+            double gx[3], gv[3];
+            /* continuity: S = m vdr F, contributes Dbar S */
+            for (int d = 0; d < 3; ++d) {
+                gx[d] = Dbar * m * (F * vv[d] + vdr * Fr * r[d]);
+                gv[d] = Dbar * m * F * r[d];
+            }
+            double gra = 0.0, grb = 0.0;
+            if (fluid_a) {
+                /* momentum: T = -m s F r with s = pa + pb + Pi, contributes Ab . T */
+                const double rb = rho[b];
+                const double Pb = ora_pressure(p, rb), cb = ora_sound(p, rb);
+                const double pb = Pb / (rb * rb);
+                const double dpb = cb * cb / (rb * rb) - 2.0 * Pb / (rb * rb * rb);
+                const double dcb = 0.5 * (p->gamma - 1.0) * cb / rb;
+                const double den = r2 + p->eta2;
+                const double mu = h * vdr / den;
+                const double cbar = 0.5 * (ca + cb), rbar = 0.5 * (ra + rb);
+                double Pi = 0.0, dPi_dmu = 0.0, dPi_dra = 0.0, dPi_drb = 0.0, dPi_dal = 0.0;
+                if (vdr < 0.0) {
+                    Pi = -p->alpha * cbar * mu / rbar;
+                    dPi_dmu = -p->alpha * cbar / rbar;
+                    dPi_dra = -p->alpha * mu * (0.5 * dca / rbar - 0.5 * cbar / (rbar * rbar));
+                    dPi_drb = -p->alpha * mu * (0.5 * dcb / rbar - 0.5 * cbar / (rbar * rbar));
+                    dPi_dal = -cbar * mu / rbar;
+                }
+                const double s = pa + pb + Pi;
+                const double Q = Ab[0] * r[0] + Ab[1] * r[1] + Ab[2] * r[2];
+                for (int d = 0; d < 3; ++d) {
+                    const double dmu_dr = h * vv[d] / den - 2.0 * mu * r[d] / den;
+                    const double dmu_dv = h * r[d] / den;
+                    gx[d] += -m * (F * Q * dPi_dmu * dmu_dr + s * Q * Fr * r[d] + s * F * Ab[d]);
+                    gv[d] += -m * F * Q * dPi_dmu * dmu_dv;
+                }
+                gra = -m * F * Q * (dpa + dPi_dra);
+                grb = -m * F * Q * (dpb + dPi_drb);
+                ab += -m * F * Q * dPi_dal;
+            }
+            for (int d = 0; d < 3; ++d) {
+                xbar[3 * a + d] += gx[d];
+                xbar[3 * b + d] -= gx[d];
+                vbar[3 * a + d] += gv[d];
+                vbar[3 * b + d] -= gv[d];
+            }
+            rhobar[a] += gra;
+            rhobar[b] += grb;
+        }
+    }
+    *alphabar += ab;
+    free(buf);
+    cells_free(&cl);
+}
+
+/* Transpose of ora_verlet for a frozen time step dt (the state arrays are
+ * those of level n, before the update; ace is the forward (A, D) of level n).
+ * In:  xb, vb, rb  = adjoints of x, v, rho at level n+1,
+ *      vpb, rpb    = adjoints of the level-(n+1) copies of v^n, rho^n.
+ * Out: abar[4 id + 0..3] = adjoints of (A, D)^n (overwritten);
+ *      xb, vb, rb  = adjoints of level n through the update only,
+ *      vpb, rpb    = adjoints of v^{n-1}, rho^{n-1}.
+ * Boundary particles: x and v fixed (their x, v adjoints are left as they
+ * are); a floored boundary density blocks its adjoint.  Excluded particles
+ * are left unchanged with zero abar.  Pinned by: rollout gradients against
+ * central finite differences.                                               */
+ORA_EXPORT void ora_verlet_vjp(int n, int nb, const double *rho, const double *rhoprev,
+                               const double *ace, double dt, long long step, const uint8_t *excl,
+                               const ora_params *p, double *xb, double *vb, double *rb,
+                               double *vpb, double *rpb, double *abar)
+{
+    const int corr = step == 0 || ((step + 1) % p->verlet_ns) == 0;
+    for (int a = 0; a < n; ++a) {
+        double *ab4 = abar + 4 * (size_t)a;
+        ab4[0] = ab4[1] = ab4[2] = ab4[3] = 0.0;
+        if (excl[a]) continue;
+        const double D = ace[4 * (size_t)a + 3];
+        double rbar1 = rb[a];
+        if (a < nb && p->bound_floor) {
+            const double r1 = corr ? rho[a] + dt * D : rhoprev[a] + 2.0 * dt * D;
+            if (r1 < p->rho0) rbar1 = 0.0;
+        }
+        if (corr) {
+            ab4[3] = dt * rbar1;
+            rb[a] = rpb[a] + rbar1;
+            rpb[a] = 0.0;
+        } else {
+            ab4[3] = 2.0 * dt * rbar1;
+            rb[a] = rpb[a];
+            rpb[a] = rbar1;
+        }
+        if (a < nb) continue;
+        for (int d = 0; d < 3; ++d) {
+            const double xb1 = xb[3 * a + d], vb1 = vb[3 * a + d];
+            ab4[d] = 0.5 * dt * dt * xb1 + (corr ? dt : 2.0 * dt) * vb1;
+            vb[3 * a + d] = dt * xb1 + vpb[3 * a + d] + (corr ? vb1 : 0.0);
+            vpb[3 * a + d] = corr ? 0.0 : vb1;
+            /* xb unchanged: x^{n+1} depends on x^n with unit weight */
+        }
+    }
+}
+
 ORA_EXPORT int ora_num_threads(void)
 {
     return omp_get_max_threads();

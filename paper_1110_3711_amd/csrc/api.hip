@@ -133,13 +133,18 @@ sph_status sph_step(const sph_grid *g, const sph_params *p, sph_state *st, const
     if (!grid_ok(g) || !params_ok(g, p) || !state_ok(st) || !dt || !dev_status || step < 0)
         return SPH_ERR_ARG;
     if (flags & ~(SPH_FIXED_DT | SPH_ADJOINT)) return SPH_ERR_ARG;
-    if (flags & SPH_ADJOINT) return SPH_ERR_ARG;  // adjoint mode not built yet
-    (void)adj;
-    if (st->n > 0 && (!ace || (!(flags & SPH_FIXED_DT) && !visc))) return SPH_ERR_ARG;
+    if (flags & SPH_ADJOINT) {
+        if (!adj) return SPH_ERR_ARG;
+        if (st->n > 0 && (!ace || !adj->pos_bar || !adj->velrho_bar || !adj->velrho_prev_bar ||
+                          !adj->ace_bar))
+            return SPH_ERR_ARG;
+    } else if (st->n > 0 && (!ace || (!(flags & SPH_FIXED_DT) && !visc))) {
+        return SPH_ERR_ARG;
+    }
     Workspace w;
     const sph_status ws_st = ws_check(g, st->n, ws, ws_bytes, &w);
     if (ws_st != SPH_OK) return ws_st;
-    return hip_status(launch_step(g, p, st, ace, visc, dt, step, flags, w, dev_status, stream));
+    return hip_status(launch_step(g, p, st, ace, visc, dt, step, flags, adj, w, dev_status, stream));
 }
 
 sph_status sph_interact_backward(const sph_grid *g, const sph_params *p, const sph_state *st,
@@ -147,9 +152,29 @@ sph_status sph_interact_backward(const sph_grid *g, const sph_params *p, const s
                                  float *velrho_bar, double *alpha_bar, void *ws,
                                  size_t ws_bytes, hipStream_t stream)
 {
-    (void)g; (void)p; (void)st; (void)cells; (void)ace_bar; (void)pos_bar; (void)velrho_bar;
-    (void)alpha_bar; (void)ws; (void)ws_bytes; (void)stream;
-    return SPH_ERR_ARG;  // not built yet
+    if (!grid_ok(g) || !params_ok(g, p) || !state_ok(st) || !cells_ok(cells) || !alpha_bar)
+        return SPH_ERR_ARG;
+    if (st->n > 0 && (!ace_bar || !pos_bar || !velrho_bar)) return SPH_ERR_ARG;
+    Workspace w;
+    const sph_status ws_st = ws_check(g, st->n, ws, ws_bytes, &w);
+    if (ws_st != SPH_OK) return ws_st;
+    return hip_status(launch_interact_backward(g, p, st, cells, ace_bar, pos_bar, velrho_bar,
+                                               alpha_bar, w, stream));
+}
+
+sph_status sph_build_cells_backward(const int32_t *perm, int32_t n, const sph_adjoint *dst_bar,
+                                    sph_adjoint *src_bar, hipStream_t stream)
+{
+    if (n < 0 || !dst_bar || !src_bar) return SPH_ERR_ARG;
+    if (n > 0 && (!perm || !dst_bar->pos_bar || !dst_bar->velrho_bar ||
+                  !dst_bar->velrho_prev_bar || !src_bar->pos_bar || !src_bar->velrho_bar ||
+                  !src_bar->velrho_prev_bar))
+        return SPH_ERR_ARG;
+    if (n > 0 && (dst_bar->pos_bar == src_bar->pos_bar ||
+                  dst_bar->velrho_bar == src_bar->velrho_bar ||
+                  dst_bar->velrho_prev_bar == src_bar->velrho_prev_bar))
+        return SPH_ERR_ARG;
+    return hip_status(launch_unsort_adjoint(perm, n, dst_bar, src_bar, stream));
 }
 
 }  // extern "C"

@@ -7,69 +7,119 @@
 //   * the (2n+1)^2 X-runs of the stencil (Section 4.4: three consecutive
 //     cells along X are one contiguous range of the sorted arrays) are staged
 //     into LDS in the frame of the target cell: each candidate's offset gets
-//     (k_b - k_a) * cell added once, in FP32;
+//     (k_b - k_a) * cell added once, in FP32 (exact for |k_b - k_a| <= 2);
 //   * one wavefront per target: 64 candidates per step are tested for
 //     r^2 < (2h)^2, survivors are compacted with a ballot into a per-wave ring
 //     in LDS, and every full batch of 64 survivors is evaluated with all lanes
 //     busy.  This removes the divergence of a thread-per-target loop (the
 //     "code divergence" problem of Section 4) without any neighbour list in
 //     HBM;
-//   * per-lane partial sums are reduced across the wave once per target and
-//     written once (Section 4.5: accumulate in registers, write at the end).
+//   * per-lane partial sums are reduced across the wave (DPP) once per target
+//     and written once (Section 4.5: accumulate in registers, write at the end).
+//
+// The target itself is one of its staged candidates: it passes the distance
+// test with r = 0 and contributes exactly zero to every sum (r_ab = 0,
+// v_ab = 0, mu = 0), so it is not filtered per candidate; it is only removed
+// from the pair count.
 #include "sph_internal.h"
 
 namespace sph {
 
 constexpr int kThreads = 512;
 constexpr int kWaves = kThreads / kWave;
-constexpr int kTile = 2048;          // candidates staged per pass
+constexpr int kTile = 2048;          // candidates staged per pass (multiple of 64)
 constexpr int kRing = 128;           // per-wave ring of compacted candidates
+constexpr int kRingAlloc = kRing + kWave;  // + one trash slot per lane
 constexpr int kMaxRuns = 2 * 25;     // types x (2n+1)^2, n <= 2
 constexpr int kMaxRunCells = 5;      // 2n+1
+constexpr int kStageIters = kTile / kThreads;
+constexpr float kFar = 1.0e30f;      // padding position: never within the support
 
 struct RunTable {
     int32_t nruns;
-    int32_t total;                      // candidates over all runs
-    int32_t vstart[kMaxRuns + 1];       // prefix of run lengths
+    int32_t total;                          // candidates over all runs
+    int32_t vstart[kMaxRuns + 1];           // prefix of run lengths
     int32_t s[kMaxRuns][kMaxRunCells + 1];  // slot starts of the run's cells, last = end
     int32_t ncx[kMaxRuns];
-    int32_t dx0[kMaxRuns];              // x0 - cx
-    float sy[kMaxRuns], sz[kMaxRuns];   // dy * cell, dz * cell
-    int32_t self_run;                   // run holding the target cell's own fluid particles
+    int32_t dx0[kMaxRuns];                  // x0 - cx
+    float sy[kMaxRuns], sz[kMaxRuns];       // dy * cell, dz * cell
+    int32_t self_run;                       // run holding the target cell's own fluid particles
 };
 
-__device__ inline float wave_sum(float v)
+// ---------------------------------------------------------------------------
+// wave reductions: DPP within rows of 16 lanes, then the four row results
+
+template <int CTRL>
+__device__ inline int dpp_i(int v)
 {
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-    return v;
+    return __builtin_amdgcn_mov_dpp(v, CTRL, 0xf, 0xf, false);
 }
 
-__device__ inline float wave_max(float v)
+template <int CTRL>
+__device__ inline float dpp_f(float v)
 {
-    for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o));
-    return v;
+    return __builtin_bit_cast(float, dpp_i<CTRL>(__builtin_bit_cast(int, v)));
+}
+
+__device__ inline float readlane_f(float v, int l)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), l));
+}
+
+// quad_perm [1,0,3,2] = 0xB1, quad_perm [2,3,0,1] = 0x4E, row_half_mirror = 0x141,
+// row_mirror = 0x140: after the four steps every lane holds its row's sum.
+__device__ inline float wave_sum(float v)
+{
+    v += dpp_f<0xB1>(v);
+    v += dpp_f<0x4E>(v);
+    v += dpp_f<0x141>(v);
+    v += dpp_f<0x140>(v);
+    return (readlane_f(v, 0) + readlane_f(v, 16)) + (readlane_f(v, 32) + readlane_f(v, 48));
+}
+
+__device__ inline unsigned wave_max_u(unsigned v)
+{
+    v = max(v, (unsigned)dpp_i<0xB1>((int)v));
+    v = max(v, (unsigned)dpp_i<0x4E>((int)v));
+    v = max(v, (unsigned)dpp_i<0x141>((int)v));
+    v = max(v, (unsigned)dpp_i<0x140>((int)v));
+    const unsigned a = (unsigned)__builtin_amdgcn_readlane((int)v, 0);
+    const unsigned b = (unsigned)__builtin_amdgcn_readlane((int)v, 16);
+    const unsigned c = (unsigned)__builtin_amdgcn_readlane((int)v, 32);
+    const unsigned d = (unsigned)__builtin_amdgcn_readlane((int)v, 48);
+    return max(max(a, b), max(c, d));
 }
 
 __device__ inline unsigned wave_sum_u(unsigned v)
 {
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-    return v;
+    v += (unsigned)dpp_i<0xB1>((int)v);
+    v += (unsigned)dpp_i<0x4E>((int)v);
+    v += (unsigned)dpp_i<0x141>((int)v);
+    v += (unsigned)dpp_i<0x140>((int)v);
+    return (unsigned)__builtin_amdgcn_readlane((int)v, 0) +
+           (unsigned)__builtin_amdgcn_readlane((int)v, 16) +
+           (unsigned)__builtin_amdgcn_readlane((int)v, 32) +
+           (unsigned)__builtin_amdgcn_readlane((int)v, 48);
 }
 
-// Build the run table of target cell c (coordinates cx, cy, cz).  FLUID:
-// candidates are boundary and fluid particles; otherwise fluid only.
+// ---------------------------------------------------------------------------
+// stencil runs of a target cell
+
+// Build the run table of target cell (cx, cy, cz).  FLUID: candidates are
+// boundary and fluid particles; otherwise fluid only.
 template <bool FLUID>
 __device__ void build_runs(const PairConsts &K, const int32_t *__restrict__ start, int32_t cx,
                            int32_t cy, int32_t cz, RunTable &R)
 {
     const int n = K.nsub;
     const int side = 2 * n + 1;
-    const int ntypes = FLUID ? 2 : 1;
-    const int nr = ntypes * side * side;
+    const int nr = (FLUID ? 2 : 1) * side * side;
     const int32_t x0 = max(cx - n, 0);
     const int32_t x1 = min(cx + n, K.nc0 - 1);
     const int ncx = x1 - x0 + 1;
-    for (int r = threadIdx.x; r < nr; r += blockDim.x) {
+    int32_t len = 0;
+    if ((int)threadIdx.x < nr) {
+        const int r = threadIdx.x;
         const int type = FLUID ? r / (side * side) : 1;  // 0 boundary, 1 fluid
         const int rr = r % (side * side);
         const int dy = rr % side - n, dz = rr / side - n;
@@ -77,114 +127,177 @@ __device__ void build_runs(const PairConsts &K, const int32_t *__restrict__ star
         const bool ok = y >= 0 && y < K.nc1 && z >= 0 && z < K.nc2;
         int32_t key0 = 0;
         if (ok) key0 = (type ? K.ncell : 0) + x0 + K.nc0 * (y + K.nc1 * z);
+        int32_t s0 = 0, se = 0;
         for (int i = 0; i <= kMaxRunCells; ++i) {
-            int32_t v = 0;
-            if (ok) v = start[key0 + min(i, ncx)];
-            R.s[r][i] = v;
+            const int32_t sv = ok ? start[key0 + min(i, ncx)] : 0;
+            R.s[r][i] = sv;
+            if (i == 0) s0 = sv;
+            if (i == ncx) se = sv;
         }
         R.ncx[r] = ok ? ncx : 0;
         R.dx0[r] = x0 - cx;
         R.sy[r] = (float)dy * K.cellf;
         R.sz[r] = (float)dz * K.cellf;
         if (type == 1 && dy == 0 && dz == 0) R.self_run = r;
+        len = ok ? se - s0 : 0;
     }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        int32_t acc = 0;
-        for (int r = 0; r < nr; ++r) {
-            R.vstart[r] = acc;
-            acc += R.ncx[r] ? R.s[r][R.ncx[r]] - R.s[r][0] : 0;
+    // inclusive scan of the run lengths over the first wavefront (nr <= 50)
+    if (threadIdx.x < kWave) {
+        const int lane = threadIdx.x;
+        int32_t v = len;
+        for (int o = 1; o < kWave; o <<= 1) {
+            const int32_t u = __shfl_up(v, o);
+            if (lane >= o) v += u;
         }
-        R.vstart[nr] = acc;
-        R.total = acc;
-        R.nruns = nr;
+        if (lane < nr) R.vstart[lane + 1] = v;
+        if (lane == 0) R.vstart[0] = 0;
+        if (lane == nr - 1) {
+            R.total = v;
+            R.nruns = nr;
+        }
     }
     __syncthreads();
 }
 
-template <bool FLUID, bool STATS>
-__global__ __launch_bounds__(kThreads) void k_interact(
-    PairConsts K, const int32_t *__restrict__ start, const int32_t *__restrict__ list,
-    const int32_t *__restrict__ info, const float4 *__restrict__ pos,
-    const float4 *__restrict__ velrho, const int32_t *__restrict__ ids, float4 *__restrict__ ace,
-    float *__restrict__ visc, int32_t *__restrict__ queue, unsigned long long *__restrict__ npairs,
-    int32_t *__restrict__ stats)
+// ---------------------------------------------------------------------------
+// pair kernel: forward (targets) and backward (gatherers) share the work
+// queue, the stencil staging and the ballot compaction.
+
+enum Kind { kFwdFluid = 0, kFwdBound = 1, kBwdFluid = 2, kBwdBound = 3 };
+
+struct PairArgs {
+    const int32_t *start, *items, *counts;
+    const float4 *pos, *velrho;
+    const int32_t *ids;
+    float4 *ace;        // forward: out (a, drho/dt); backward: in (abar, Dbar)
+    float *visc;        // forward: out max |mu|
+    float4 *xbar;       // backward: pos_bar (+=)
+    float4 *vbar;       // backward: velrho_bar (+=)
+    float *alpha_part;  // backward: per-slot alpha adjoint of fluid targets
+    int32_t *queue;
+    unsigned long long *npairs;
+    int32_t *stats;
+};
+
+template <int KIND>
+struct KindTraits {
+    static constexpr bool fluid = KIND == kFwdFluid || KIND == kBwdFluid;
+    static constexpr bool bwd = KIND >= kBwdFluid;
+    static constexpr int tile = bwd ? 1536 : kTile;  // LDS: 32 B (forward) / 48 B per candidate
+};
+
+template <int KIND, bool STATS>
+__global__ __launch_bounds__(kThreads) void k_interact(PairConsts K, PairArgs A)
 {
-    __shared__ float4 sP[kTile];                  // (offset in target frame, P/rho^2)
-    __shared__ float4 sV[kTile];                  // (v, rho - rho0)
-    __shared__ uint16_t sRing[kWaves][kRing];
-    __shared__ int32_t sSlot[STATS ? kTile : 1];  // candidate slot (diagnostics only)
+    using T = KindTraits<KIND>;
+    constexpr bool FLUID = T::fluid;
+    constexpr bool BWD = T::bwd;
+    constexpr int TILE = T::tile;
+    constexpr int STAGE = TILE / kThreads;
+    __shared__ float4 sP[TILE];                   // (offset in target frame, P/rho^2)
+    __shared__ float4 sV[TILE];                   // (v, rho - rho0)
+    __shared__ float4 sA[BWD ? TILE : 1];         // backward: (abar, Dbar), abar = 0 on boundary
+    __shared__ uint16_t sRing[kWaves][kRingAlloc];
+    __shared__ int32_t sSlot[STATS ? TILE : 1];   // candidate slot (diagnostics only)
     __shared__ RunTable R;
     __shared__ int32_t sItem;
 
     const int lane = threadIdx.x & (kWave - 1);
     const int wave = threadIdx.x / kWave;
-    // counts come from sph_build_cells on the same stream; clamp them so that
-    // inconsistent inputs can never index outside [0, n)
-    const int32_t nbc = min(max(info[0], 0), K.n);
-    const int32_t ibase = FLUID ? nbc : 0;
-    const int32_t nitems = FLUID ? min(max(info[1], 0), K.n - nbc) : nbc;
+    // Work items: fluid cells are list[info[0] .. info[0] + info[1]); boundary
+    // cells with fluid in reach are active[0 .. nactive).  Counts are clamped
+    // so that inconsistent inputs can never index outside [0, n).
+    int32_t ibase, nitems;
+    if (FLUID) {
+        ibase = min(max(A.counts[0], 0), K.n);
+        nitems = min(max(A.counts[1], 0), K.n - ibase);
+    } else {
+        ibase = 0;
+        nitems = min(max(A.counts[0], 0), K.n);
+    }
     unsigned long long pairs_acc = 0;  // wave-uniform
 
     for (;;) {
-        if (threadIdx.x == 0) sItem = atomicAdd(queue, 1);
+        if (threadIdx.x == 0) sItem = atomicAdd(A.queue, 1);
         __syncthreads();
         const int32_t item = sItem;
         if (item >= nitems) break;
-        const int32_t key = min(max(list[ibase + item], 0), 2 * K.ncell - 1);
+        const int32_t key = min(max(A.items[ibase + item], 0), 2 * K.ncell - 1);
         const int32_t c = FLUID ? max(key - K.ncell, 0) : min(key, K.ncell - 1);
         const int32_t cx = c % K.nc0, cy = (c / K.nc0) % K.nc1, cz = c / (K.nc0 * K.nc1);
-        const int32_t tbeg = min(max(start[key], 0), K.n);
-        const int32_t tend = min(max(start[key + 1], tbeg), K.n);
+        const int32_t tbeg = min(max(A.start[key], 0), K.n);
+        const int32_t tend = min(max(A.start[key + 1], tbeg), K.n);
 
-        build_runs<FLUID>(K, start, cx, cy, cz, R);
+        build_runs<FLUID>(K, A.start, cx, cy, cz, R);
         const int32_t total = R.total;
         const int nr = R.nruns;
+        const int nbruns = FLUID ? nr / 2 : 0;  // runs [0, nbruns) hold boundary particles
 
-        if (!FLUID && total == 0) {
-            // boundary cell with no fluid in reach
-            for (int32_t a = tbeg + threadIdx.x; a < tend; a += blockDim.x) {
-                ace[a] = make_float4(0.f, 0.f, 0.f, 0.f);
-                visc[a] = 0.f;
-                if (STATS) { stats[2 * a] = 0; stats[2 * a + 1] = 0; }
-            }
-            __syncthreads();
-            continue;
-        }
-
-        for (int32_t tb = 0; tb < max(total, 1); tb += kTile) {
-            const int32_t tlen = min(kTile, total - tb);
-            // ---- stage candidates [tb, tb + tlen) into LDS
-            for (int32_t l = threadIdx.x; l < tlen; l += blockDim.x) {
-                const int32_t v = tb + l;
-                int lo = 0, hi = nr;  // find r with vstart[r] <= v < vstart[r+1]
-                while (hi - lo > 1) {
-                    const int mid = (lo + hi) >> 1;
-                    if (R.vstart[mid] <= v) lo = mid;
-                    else hi = mid;
+        for (int32_t tb = 0; tb < max(total, 1); tb += TILE) {
+            const int32_t tlen = max(min(TILE, total - tb), 0);
+            const int32_t tpad = (tlen + kWave - 1) & ~(kWave - 1);
+            // ---- stage candidates [tb, tb + tlen) into LDS; pad to a multiple of 64
+#pragma unroll
+            for (int u = 0; u < STAGE; ++u) {
+                const int32_t l = threadIdx.x + u * kThreads;
+                if (l < tlen) {
+                    const int32_t v = tb + l;
+                    int lo = 0, hi = nr;  // find r with vstart[r] <= v < vstart[r+1]
+                    while (hi - lo > 1) {
+                        const int mid = (lo + hi) >> 1;
+                        if (R.vstart[mid] <= v) lo = mid;
+                        else hi = mid;
+                    }
+                    const int32_t j = min(max(R.s[lo][0] + (v - R.vstart[lo]), 0), K.n - 1);
+                    int ci = 0;
+                    for (int i = 1; i < R.ncx[lo]; ++i) ci += R.s[lo][i] <= j ? 1 : 0;
+                    const float sx = (float)(R.dx0[lo] + ci) * K.cellf;  // (k_b - k_a) cell, exact
+                    const float4 p = A.pos[j];
+                    sP[l] = make_float4(p.x + sx, p.y + R.sy[lo], p.z + R.sz[lo], p.w);
+                    sV[l] = A.velrho[j];
+                    if (BWD) {
+                        float4 ab = A.ace[j];
+                        if (lo < nbruns) ab.x = ab.y = ab.z = 0.f;
+                        sA[l] = ab;
+                    }
+                    if (STATS) sSlot[l] = j;
+                } else if (l < tpad) {
+                    sP[l] = make_float4(kFar, kFar, kFar, 0.f);
                 }
-                const int r = lo;
-                const int32_t j = min(max(R.s[r][0] + (v - R.vstart[r]), 0), K.n - 1);
-                int ci = 0;
-                for (int i = 1; i < R.ncx[r]; ++i) ci += R.s[r][i] <= j ? 1 : 0;
-                const float4 p = pos[j];
-                const float sx = (float)(R.dx0[r] + ci) * K.cellf;  // (k_b - k_a) cell, exact
-                sP[l] = make_float4(p.x + sx, p.y + R.sy[r], p.z + R.sz[r], p.w);
-                sV[l] = velrho[j];
-                if (STATS) sSlot[l] = j;
             }
             __syncthreads();
 
             // ---- one wavefront per target
             const int32_t selfbase = FLUID ? R.vstart[R.self_run] - R.s[R.self_run][0] - tb : 0;
             for (int32_t a = tbeg + wave; a < tend; a += kWaves) {
-                const float4 pa = pos[a];
-                const float4 va = velrho[a];
                 const int32_t self_l = FLUID ? selfbase + a : -1;
-                const float rhoa = K.rho0 + va.w;
-                const float ta = rhoa * K.inv_rho0;
-                const float ca = K.c0 * ta * ta * ta;
-                float sx = 0.f, sy = 0.f, sz = 0.f, sd = 0.f, vm = 0.f;
+                const bool self_here = FLUID && self_l >= 0 && self_l < tlen;
+                float4 pa, va, aa = make_float4(0.f, 0.f, 0.f, 0.f);
+                if (self_here) {
+                    pa = sP[self_l];
+                    va = sV[self_l];
+                    if (BWD) aa = sA[self_l];
+                } else {
+                    pa = A.pos[a];
+                    va = A.velrho[a];
+                    if (BWD && FLUID) aa = A.ace[a];
+                }
+                // t = rho / rho0; the Monaghan factor cbar / rhobar for c = c0 t^3 is
+                // (c0 / rho0) (ta^3 + tb^3) / (ta + tb) = (c0 / rho0) (ta^2 - ta tb + tb^2)
+                const float ta = __builtin_fmaf(va.w, K.inv_rho0, 1.0f);
+                const float ta2 = ta * ta;
+                // backward: d(P/rho^2)/drho = c^2 / rho^2 - 2 (P/rho^2) / rho, c = c0 ta^3
+                float dpa = 0.f;
+                if (BWD) {
+                    const float inv_ra = __builtin_amdgcn_rcpf(K.rho0 * ta);
+                    const float ca = K.c0 * ta2 * ta;
+                    dpa = (ca * inv_ra) * (ca * inv_ra) - 2.f * pa.w * inv_ra;
+                }
+                // accumulators: forward (s0..s3 = sum for a.xyz and drho, vmb = max |mu|);
+                // backward (s0..s2 = xbar, s4..s6 = vbar, s3 = rhobar, s7 = alphabar)
+                float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f, s4 = 0.f, s5 = 0.f, s6 = 0.f,
+                      s7 = 0.f;
+                unsigned vmb = 0u;  // bits of max |mu| (non-negative floats order as integers)
                 unsigned hs = 0;
                 int wp = 0, rp = 0;
 
@@ -198,98 +311,222 @@ __global__ __launch_bounds__(kThreads) void k_interact(
                     const float F = K.kf * (wq * wq * wq);
                     const float vx = va.x - vb.x, vy = va.y - vb.y, vz = va.z - vb.z;
                     const float vdr = __builtin_fmaf(vz, rz, __builtin_fmaf(vy, ry, vx * rx));
-                    sd = __builtin_fmaf(vdr, F, sd);
-                    if (FLUID) {
-                        const float rhob = K.rho0 + vb.w;
-                        const float mu = K.h * vdr * __builtin_amdgcn_rcpf(r2 + K.eta2);
-                        vm = fmaxf(vm, fabsf(mu));
-                        const float tb3 = rhob * K.inv_rho0;
-                        const float cb = K.c0 * tb3 * tb3 * tb3;
-                        const float pi = vdr < 0.f
-                                             ? -K.alpha * (ca + cb) * mu * __builtin_amdgcn_rcpf(rhoa + rhob)
-                                             : 0.f;
-                        const float coef = (pa.w + pb.w + pi) * F;
-                        sx = __builtin_fmaf(coef, rx, sx);
-                        sy = __builtin_fmaf(coef, ry, sy);
-                        sz = __builtin_fmaf(coef, rz, sz);
+                    if (!BWD) {
+                        s3 = __builtin_fmaf(vdr, F, s3);
+                        if (FLUID) {
+                            const float mu = K.h * vdr * __builtin_amdgcn_rcpf(r2 + K.eta2);
+                            vmb = max(vmb, __builtin_bit_cast(unsigned, fabsf(mu)));
+                            const float tb = __builtin_fmaf(vb.w, K.inv_rho0, 1.0f);
+                            const float cr = __builtin_fmaf(tb, tb - ta, ta2);
+                            // Monaghan term, active only for approaching pairs (mu < 0):
+                            // -alpha cbar mu / rhobar = -alpha (c0/rho0) cr min(mu, 0)
+                            const float pi = K.kpi * cr * fminf(mu, 0.f);
+                            const float coef = (pa.w + pb.w + pi) * F;
+                            s0 = __builtin_fmaf(coef, rx, s0);
+                            s1 = __builtin_fmaf(coef, ry, s1);
+                            s2 = __builtin_fmaf(coef, rz, s2);
+                        }
+                        if (STATS) hs += (uint32_t)A.ids[sSlot[idx]] * 2654435761u;
+                    } else {
+                        // Pair contribution to the loss, symmetric in (a, b):
+                        //   (abar_a - abar_b) . T_ab + (Dbar_a + Dbar_b) S_ab,
+                        //   T_ab = -m s F r_ab, s = P_a/rho_a^2 + P_b/rho_b^2 + Pi_ab,
+                        //   S_ab = m (v_ab . r_ab) F;  its derivatives w.r.t. the gatherer a.
+                        const float4 ab = sA[idx];
+                        const float dax = aa.x - ab.x, day = aa.y - ab.y, daz = aa.z - ab.z;
+                        const float Q = __builtin_fmaf(daz, rz, __builtin_fmaf(day, ry, dax * rx));
+                        const float tb = __builtin_fmaf(vb.w, K.inv_rho0, 1.0f);
+                        const float cr = __builtin_fmaf(tb, tb - ta, ta2);
+                        const float invden = __builtin_amdgcn_rcpf(r2 + K.eta2);
+                        const float mu = K.h * vdr * invden;
+                        const float mneg = fminf(mu, 0.f);
+                        // d/drho_a of s: d(P/rho^2)/drho + dPi/drho_a
+                        const float dpi_dra = K.kpi * K.inv_rho0 * __builtin_fmaf(2.f, ta, -tb) * mneg;
+                        s3 = __builtin_fmaf(-F * Q, dpa + dpi_dra, s3);
+                        if (FLUID) {
+                            // dF/dr / r = -(3 kf / 2h) wq^2 / r; 0 for the self pair
+                            const float Fr = r2 > 0.f ? K.kfr * wq * wq * __builtin_amdgcn_rcpf(r)
+                                                      : 0.f;
+                            // continuity
+                            const float sD = aa.w + ab.w;
+                            const float c1 = sD * F, c2 = sD * vdr * Fr;
+                            // momentum
+                            const float pi = K.kpi * cr * mneg;
+                            const float sm = pa.w + pb.w + pi;
+                            const float dpi_dmu = mu < 0.f ? K.kpi * cr : 0.f;
+                            const float e1 = F * Q * dpi_dmu;
+                            const float e1h = e1 * K.h * invden;
+                            const float e2 = __builtin_fmaf(-2.f * e1 * invden, mu, sm * Q * Fr);
+                            const float e3 = sm * F;
+                            s0 += __builtin_fmaf(c1, vx, c2 * rx) - __builtin_fmaf(e1h, vx, __builtin_fmaf(e2, rx, e3 * dax));
+                            s1 += __builtin_fmaf(c1, vy, c2 * ry) - __builtin_fmaf(e1h, vy, __builtin_fmaf(e2, ry, e3 * day));
+                            s2 += __builtin_fmaf(c1, vz, c2 * rz) - __builtin_fmaf(e1h, vz, __builtin_fmaf(e2, rz, e3 * daz));
+                            const float g = c1 - e1h;
+                            s4 = __builtin_fmaf(g, rx, s4);
+                            s5 = __builtin_fmaf(g, ry, s5);
+                            s6 = __builtin_fmaf(g, rz, s6);
+                            // alpha: own target term abar_a . dA_a/dalpha, dPi/dalpha = Pi/alpha
+                            const float qa = __builtin_fmaf(aa.z, rz, __builtin_fmaf(aa.y, ry, aa.x * rx));
+                            s7 = __builtin_fmaf(-F * qa, K.kpa * cr * mneg, s7);
+                        }
                     }
-                    if (STATS) hs += (uint32_t)ids[sSlot[idx]] * 2654435761u;
                 };
 
-                for (int32_t cb0 = 0; cb0 < tlen; cb0 += kWave) {
-                    const int32_t j = cb0 + lane;
-                    bool pass = false;
-                    if (j < tlen) {
-                        const float4 pb = sP[j];
-                        const float rx = pa.x - pb.x, ry = pa.y - pb.y, rz = pa.z - pb.z;
-                        const float r2 = __builtin_fmaf(rz, rz, __builtin_fmaf(ry, ry, rx * rx));
-                        pass = r2 < K.rc2 && j != self_l;
-                    }
+                // test one chunk of 64 staged candidates; survivors go to the ring,
+                // full batches of 64 are evaluated at once
+                auto chunk = [&](const float4 pb, int32_t cb0) {
+                    const float rx = pa.x - pb.x, ry = pa.y - pb.y, rz = pa.z - pb.z;
+                    const float r2 = __builtin_fmaf(rz, rz, __builtin_fmaf(ry, ry, rx * rx));
+                    const bool pass = r2 < K.rc2;
                     const unsigned long long m = ballot(pass);
-                    if (pass) sRing[wave][(wp + (int)lane_rank(m)) & (kRing - 1)] = (uint16_t)j;
+                    const int slot = pass ? ((wp + (int)lane_rank(m)) & (kRing - 1)) : kRing + lane;
+                    sRing[wave][slot] = (uint16_t)(cb0 + lane);
                     wp += __popcll(m);
                     if (wp - rp >= kWave) {
                         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
                         pair(sRing[wave][(rp + lane) & (kRing - 1)]);
                         rp += kWave;
                     }
+                };
+                // two chunks per iteration, each prefetched one chunk ahead
+                float4 p0 = sP[lane];
+                float4 p1 = tpad > kWave ? sP[kWave + lane] : p0;
+                int32_t cb0 = 0;
+                for (; cb0 + 2 * kWave <= tpad; cb0 += 2 * kWave) {
+                    const float4 c0 = p0;
+                    if (cb0 + 2 * kWave < tpad) p0 = sP[cb0 + 2 * kWave + lane];
+                    chunk(c0, cb0);
+                    const float4 c1 = p1;
+                    if (cb0 + 3 * kWave < tpad) p1 = sP[cb0 + 3 * kWave + lane];
+                    chunk(c1, cb0 + kWave);
                 }
+                if (cb0 < tpad) chunk(p0, cb0);
                 if (wp > rp) {
                     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
                     if (lane < wp - rp) pair(sRing[wave][(rp + lane) & (kRing - 1)]);
                 }
-                pairs_acc += (unsigned long long)wp;
+                const int cnt = wp - (self_here ? 1 : 0);
+                pairs_acc += (unsigned long long)cnt;
 
                 // ---- reduce over the wave, write (first tile) or accumulate
-                const float tsd = wave_sum(sd);
-                float tsx = 0.f, tsy = 0.f, tsz = 0.f, tvm = 0.f;
-                if (FLUID) {
-                    tsx = wave_sum(sx);
-                    tsy = wave_sum(sy);
-                    tsz = wave_sum(sz);
-                    tvm = wave_max(vm);
-                }
-                unsigned ths = 0;
-                if (STATS) ths = wave_sum_u(hs);
-                if (lane == 0) {
-                    float4 o;
-                    if (FLUID)
-                        o = make_float4(-K.mass * tsx, -K.mass * tsy, -K.mass * tsz, K.mass * tsd);
-                    else
-                        o = make_float4(0.f, 0.f, 0.f, K.mass * tsd);
-                    if (tb == 0) {
-                        if (FLUID) { o.x += K.gx; o.y += K.gy; o.z += K.gz; }
-                        ace[a] = o;
-                        visc[a] = tvm;
-                        if (STATS) { stats[2 * a] = wp; stats[2 * a + 1] = (int32_t)ths; }
-                    } else {
-                        float4 p0 = ace[a];
-                        p0.x += o.x; p0.y += o.y; p0.z += o.z; p0.w += o.w;
-                        ace[a] = p0;
-                        visc[a] = fmaxf(visc[a], tvm);
-                        if (STATS) {
-                            stats[2 * a] += wp;
-                            stats[2 * a + 1] = (int32_t)((uint32_t)stats[2 * a + 1] + ths);
+                if (!BWD) {
+                    const float tsd = wave_sum(s3);
+                    float tsx = 0.f, tsy = 0.f, tsz = 0.f, tvm = 0.f;
+                    if (FLUID) {
+                        tsx = wave_sum(s0);
+                        tsy = wave_sum(s1);
+                        tsz = wave_sum(s2);
+                        tvm = __builtin_bit_cast(float, wave_max_u(vmb));
+                    }
+                    unsigned ths = 0;
+                    if (STATS) {
+                        ths = wave_sum_u(hs);
+                        if (self_here) ths -= (uint32_t)A.ids[a] * 2654435761u;
+                    }
+                    if (lane == 0) {
+                        float4 o;
+                        if (FLUID)
+                            o = make_float4(-K.mass * tsx, -K.mass * tsy, -K.mass * tsz,
+                                            K.mass * tsd);
+                        else
+                            o = make_float4(0.f, 0.f, 0.f, K.mass * tsd);
+                        if (tb == 0) {
+                            if (FLUID) { o.x += K.gx; o.y += K.gy; o.z += K.gz; }
+                            A.ace[a] = o;
+                            A.visc[a] = tvm;
+                            if (STATS) { A.stats[2 * a] = cnt; A.stats[2 * a + 1] = (int32_t)ths; }
+                        } else {
+                            float4 p0s = A.ace[a];
+                            p0s.x += o.x; p0s.y += o.y; p0s.z += o.z; p0s.w += o.w;
+                            A.ace[a] = p0s;
+                            A.visc[a] = fmaxf(A.visc[a], tvm);
+                            if (STATS) {
+                                A.stats[2 * a] += cnt;
+                                A.stats[2 * a + 1] = (int32_t)((uint32_t)A.stats[2 * a + 1] + ths);
+                            }
                         }
+                    }
+                } else {
+                    const float tr = wave_sum(s3);
+                    float t0 = 0.f, t1 = 0.f, t2 = 0.f, t4 = 0.f, t5 = 0.f, t6 = 0.f, t7 = 0.f;
+                    if (FLUID) {
+                        t0 = wave_sum(s0);
+                        t1 = wave_sum(s1);
+                        t2 = wave_sum(s2);
+                        t4 = wave_sum(s4);
+                        t5 = wave_sum(s5);
+                        t6 = wave_sum(s6);
+                        t7 = wave_sum(s7);
+                    }
+                    if (lane == 0) {
+                        float4 vbo = A.vbar[a];
+                        vbo.w += K.mass * tr;
+                        if (FLUID) {
+                            float4 xbo = A.xbar[a];
+                            xbo.x += K.mass * t0;
+                            xbo.y += K.mass * t1;
+                            xbo.z += K.mass * t2;
+                            A.xbar[a] = xbo;
+                            vbo.x += K.mass * t4;
+                            vbo.y += K.mass * t5;
+                            vbo.z += K.mass * t6;
+                            A.alpha_part[a] = (tb == 0 ? 0.f : A.alpha_part[a]) + K.mass * t7;
+                        }
+                        A.vbar[a] = vbo;
                     }
                 }
             }
             __syncthreads();
         }
     }
-    if (npairs && lane == 0 && pairs_acc) atomicAdd(npairs, pairs_acc);
+    if (A.npairs && lane == 0 && pairs_acc) atomicAdd(A.npairs, pairs_acc);
 }
 
-__global__ void k_zero_queue(int32_t *q)
+// Boundary cells: those with fluid particles in their stencil go to the work
+// list of the B-F kernel; the others have no neighbours and get zero outputs.
+__global__ void k_bound_filter(PairConsts K, const int32_t *__restrict__ start,
+                               const int32_t *__restrict__ list, const int32_t *__restrict__ info,
+                               int32_t *__restrict__ active, int32_t *__restrict__ nactive,
+                               float4 *__restrict__ ace, float *__restrict__ visc,
+                               int32_t *__restrict__ stats)
 {
-    if (threadIdx.x == 0) q[0] = 0;
+    const int32_t nbc = min(max(info[0], 0), K.n);
+    const int n = K.nsub;
+    for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < nbc; i += gridDim.x * blockDim.x) {
+        const int32_t key = min(max(list[i], 0), K.ncell - 1);
+        const int32_t cx = key % K.nc0, cy = (key / K.nc0) % K.nc1, cz = key / (K.nc0 * K.nc1);
+        const int32_t x0 = max(cx - n, 0), x1 = min(cx + n, K.nc0 - 1);
+        int32_t total = 0;
+        for (int dz = -n; dz <= n; ++dz)
+            for (int dy = -n; dy <= n; ++dy) {
+                const int32_t y = cy + dy, z = cz + dz;
+                if (y < 0 || y >= K.nc1 || z < 0 || z >= K.nc2) continue;
+                const int32_t k0 = K.ncell + x0 + K.nc0 * (y + K.nc1 * z);
+                total += start[k0 + (x1 - x0 + 1)] - start[k0];
+            }
+        if (total > 0) {
+            active[atomicAdd(nactive, 1)] = key;
+        } else if (ace) {
+            const int32_t b = min(max(start[key], 0), K.n), e = min(max(start[key + 1], b), K.n);
+            for (int32_t a = b; a < e; ++a) {
+                ace[a] = make_float4(0.f, 0.f, 0.f, 0.f);
+                visc[a] = 0.f;
+                if (stats) { stats[2 * a] = 0; stats[2 * a + 1] = 0; }
+            }
+        }
+    }
+}
+
+__global__ void k_zero_counters(int32_t *q, int count)
+{
+    if ((int)threadIdx.x < count) q[threadIdx.x] = 0;
 }
 
 // Excluded particles (the tail of the sorted state) get zero outputs.
 __global__ void k_zero_excluded(int32_t n, const int32_t *__restrict__ info, float4 *__restrict__ ace,
                                 float *__restrict__ visc, int32_t *__restrict__ stats)
 {
-    const int32_t nex = info[2];
+    const int32_t nex = min(max(info[2], 0), n);
     for (int32_t i = n - nex + blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += gridDim.x * blockDim.x) {
         ace[i] = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -298,7 +535,7 @@ __global__ void k_zero_excluded(int32_t n, const int32_t *__restrict__ info, flo
     }
 }
 
-static PairConsts pair_consts(const sph_grid *g, const sph_params *p)
+static PairConsts pair_consts(const sph_grid *g, const sph_params *p, int32_t n)
 {
     PairConsts K;
     const double pi = 3.14159265358979323846;
@@ -310,7 +547,9 @@ static PairConsts pair_consts(const sph_grid *g, const sph_params *p)
     K.inv_h = (float)(1.0 / h);
     K.kf = (float)(-5.0 * ad / (h * h));
     K.eta2 = (float)p->eta2;
-    K.alpha = (float)p->alpha;
+    K.kpi = (float)(-p->alpha * p->c0 / p->rho0);
+    K.kpa = (float)(-p->c0 / p->rho0);
+    K.kfr = (float)(1.5 * 5.0 * ad / (h * h * h));
     K.c0 = (float)p->c0;
     K.rho0 = (float)p->rho0;
     K.inv_rho0 = (float)(1.0 / p->rho0);
@@ -323,29 +562,44 @@ static PairConsts pair_consts(const sph_grid *g, const sph_params *p)
     K.nc1 = g->nc[1];
     K.nc2 = g->nc[2];
     K.ncell = (int32_t)ncell_of(g);
-    K.n = 0;
+    K.n = n;
     return K;
 }
 
-template <bool FLUID, bool STATS>
-static hipError_t launch_one(const PairConsts &K, const sph_state *st, const sph_cells *cells,
-                             float *ace, float *visc, unsigned long long *npairs, int32_t *stats,
-                             int32_t *queue, hipStream_t s)
+template <int KIND, bool STATS>
+static hipError_t launch_one(const PairConsts &K, const PairArgs &A, hipStream_t s)
 {
     int dev = 0, cus = 0, occ = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return e;
     e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     if (e != hipSuccess) return e;
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_interact<FLUID, STATS>, kThreads, 0);
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_interact<KIND, STATS>, kThreads, 0);
     if (e != hipSuccess) return e;
     if (cus <= 0) cus = 1;
     if (occ <= 0) occ = 1;
-    const int grid = cus * occ;
-    k_interact<FLUID, STATS><<<grid, kThreads, 0, s>>>(
-        K, cells->start, cells->list, cells->info, (const float4 *)st->pos,
-        (const float4 *)st->velrho, st->id, (float4 *)ace, visc, queue, npairs, stats);
+    k_interact<KIND, STATS><<<cus * occ, kThreads, 0, s>>>(K, A);
     return hipGetLastError();
+}
+
+static PairArgs base_args(const sph_state *st, const sph_cells *cells)
+{
+    PairArgs A;
+    A.start = cells->start;
+    A.items = cells->list;
+    A.counts = cells->info;
+    A.pos = (const float4 *)st->pos;
+    A.velrho = (const float4 *)st->velrho;
+    A.ids = st->id;
+    A.ace = nullptr;
+    A.visc = nullptr;
+    A.xbar = nullptr;
+    A.vbar = nullptr;
+    A.alpha_part = nullptr;
+    A.queue = nullptr;
+    A.npairs = nullptr;
+    A.stats = nullptr;
+    return A;
 }
 
 hipError_t launch_interact(const sph_grid *g, const sph_params *p, const sph_state *st,
@@ -354,26 +608,100 @@ hipError_t launch_interact(const sph_grid *g, const sph_params *p, const sph_sta
                            hipStream_t s)
 {
     if (st->n == 0) return hipSuccess;
-    PairConsts K = pair_consts(g, p);
-    K.n = st->n;
+    const PairConsts K = pair_consts(g, p, st->n);
+    PairArgs A = base_args(st, cells);
+    A.ace = (float4 *)ace;
+    A.visc = visc;
+    A.npairs = npairs;
+    A.stats = nbr_stats;
+    // counters: [0] fluid queue, [1] boundary queue, [2] active boundary cells
     hipError_t e = hipSuccess;
     if (parts & SPH_PI_FLUID) {
-        k_zero_queue<<<1, 64, 0, s>>>(w.counters + 0);
-        e = nbr_stats ? launch_one<true, true>(K, st, cells, ace, visc, npairs, nbr_stats,
-                                               w.counters + 0, s)
-                      : launch_one<true, false>(K, st, cells, ace, visc, npairs, nullptr,
-                                                w.counters + 0, s);
+        k_zero_counters<<<1, 64, 0, s>>>(w.counters + 0, 1);
+        A.queue = w.counters + 0;
+        e = nbr_stats ? launch_one<kFwdFluid, true>(K, A, s) : launch_one<kFwdFluid, false>(K, A, s);
         if (e != hipSuccess) return e;
     }
     if (parts & SPH_PI_BOUNDARY) {
-        k_zero_queue<<<1, 64, 0, s>>>(w.counters + 1);
+        k_zero_counters<<<1, 64, 0, s>>>(w.counters + 1, 2);
         k_zero_excluded<<<64, 256, 0, s>>>(st->n, cells->info, (float4 *)ace, visc, nbr_stats);
-        e = nbr_stats ? launch_one<false, true>(K, st, cells, ace, visc, npairs, nbr_stats,
-                                                w.counters + 1, s)
-                      : launch_one<false, false>(K, st, cells, ace, visc, npairs, nullptr,
-                                                 w.counters + 1, s);
+        k_bound_filter<<<256, 256, 0, s>>>(K, cells->start, cells->list, cells->info, w.active,
+                                           w.counters + 2, (float4 *)ace, visc, nbr_stats);
+        A.items = w.active;
+        A.counts = w.counters + 2;
+        A.queue = w.counters + 1;
+        e = nbr_stats ? launch_one<kFwdBound, true>(K, A, s) : launch_one<kFwdBound, false>(K, A, s);
     }
     return e;
+}
+
+// Deterministic FP64 sum of the per-slot alpha adjoints of the fluid slots
+// [nb, n - excluded): fixed-order block partials, then one block.
+__global__ __launch_bounds__(kReduceThreads) void k_alpha_partial(int32_t n, int32_t nb,
+                                                                  const int32_t *__restrict__ info,
+                                                                  const float *__restrict__ part,
+                                                                  double *__restrict__ out)
+{
+    __shared__ double sh[kReduceThreads];
+    const int32_t hi = n - min(max(info[2], 0), n);
+    double acc = 0.0;
+    for (int32_t i = nb + blockIdx.x * blockDim.x + threadIdx.x; i < hi; i += gridDim.x * blockDim.x)
+        acc += (double)part[i];
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int o = kReduceThreads / 2; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[blockIdx.x] = sh[0];
+}
+
+__global__ __launch_bounds__(kReduceThreads) void k_alpha_final(int nblk, const double *__restrict__ in,
+                                                                double *__restrict__ alpha_bar)
+{
+    __shared__ double sh[kReduceThreads];
+    double acc = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += kReduceThreads) acc += in[b];
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int o = kReduceThreads / 2; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) alpha_bar[0] += sh[0];
+}
+
+hipError_t launch_interact_backward(const sph_grid *g, const sph_params *p, const sph_state *st,
+                                    const sph_cells *cells, const float *ace_bar, float *pos_bar,
+                                    float *velrho_bar, double *alpha_bar, const Workspace &w,
+                                    hipStream_t s)
+{
+    if (st->n == 0) return hipSuccess;
+    const PairConsts K = pair_consts(g, p, st->n);
+    PairArgs A = base_args(st, cells);
+    A.ace = (float4 *)ace_bar;
+    A.xbar = (float4 *)pos_bar;
+    A.vbar = (float4 *)velrho_bar;
+    A.alpha_part = w.alpha_part;
+    k_zero_counters<<<1, 64, 0, s>>>(w.counters + 3, 3);
+    A.queue = w.counters + 3;
+    hipError_t e = launch_one<kBwdFluid, false>(K, A, s);
+    if (e != hipSuccess) return e;
+    // boundary gatherers: only cells with fluid in reach have non-zero terms
+    k_bound_filter<<<256, 256, 0, s>>>(K, cells->start, cells->list, cells->info, w.active,
+                                       w.counters + 5, nullptr, nullptr, nullptr);
+    A.items = w.active;
+    A.counts = w.counters + 5;
+    A.queue = w.counters + 4;
+    e = launch_one<kBwdBound, false>(K, A, s);
+    if (e != hipSuccess) return e;
+    int nblk = (int)(((int64_t)st->n + kReduceThreads - 1) / kReduceThreads);
+    if (nblk > kReduceBlocksMax) nblk = kReduceBlocksMax;
+    if (nblk < 1) nblk = 1;
+    k_alpha_partial<<<nblk, kReduceThreads, 0, s>>>(st->n, st->nb, cells->info, w.alpha_part,
+                                                    w.reduce);
+    k_alpha_final<<<1, kReduceThreads, 0, s>>>(nblk, w.reduce, alpha_bar);
+    return hipGetLastError();
 }
 
 }  // namespace sph

@@ -34,6 +34,8 @@ struct Workspace {
     unsigned long long *partials;             // scan partial sums
     unsigned long long *keyscan;              // [nkeys + 1] packed (count << 32 | nonempty)
     int32_t *counters;                        // [16] work queues and flags
+    int32_t *active;                          // [n] boundary cells with fluid in reach
+    float *alpha_part;                        // [n] per-slot alpha adjoint
     double *reduce;                           // [3 * kReduceBlocksMax] CFL partials
     size_t bytes;
 };
@@ -64,6 +66,8 @@ inline bool layout_workspace(const sph_grid *g, int64_t n, void *base, Workspace
     const size_t o_p = take(sizeof(unsigned long long) * np);
     const size_t o_ks = take(sizeof(unsigned long long) * (size_t)(nkeys + 1));
     const size_t o_c = take(sizeof(int32_t) * 16);
+    const size_t o_a = take(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+    const size_t o_ap = take(sizeof(float) * (size_t)(n > 0 ? n : 1));
     const size_t o_r = take(sizeof(double) * 3 * kReduceBlocksMax);
     w->bytes = off;
     if (base) {
@@ -76,6 +80,8 @@ inline bool layout_workspace(const sph_grid *g, int64_t n, void *base, Workspace
         w->partials = (unsigned long long *)(b + o_p);
         w->keyscan = (unsigned long long *)(b + o_ks);
         w->counters = (int32_t *)(b + o_c);
+        w->active = (int32_t *)(b + o_a);
+        w->alpha_part = (float *)(b + o_ap);
         w->reduce = (double *)(b + o_r);
     }
     return true;
@@ -89,7 +95,9 @@ struct PairConsts {
     float inv_h;     // 1/h
     float kf;        // F = kf (1 - q/2)^3, kf = -5 aD / h^2, aD = 21 / (16 pi h^3)
     float eta2;
-    float alpha;
+    float kpi;       // -alpha c0 / rho0
+    float kpa;       // -c0 / rho0 (d Pi / d alpha per unit cr min(mu, 0))
+    float kfr;       // (dF/dr)/r = kfr (1 - q/2)^2 / r, kfr = -3 kf / (2h)
     float c0;
     float rho0;
     float inv_rho0;
@@ -113,9 +121,15 @@ hipError_t launch_interact(const sph_grid *g, const sph_params *p, const sph_sta
                            const sph_cells *cells, unsigned parts, float *ace, float *visc,
                            unsigned long long *npairs, int32_t *nbr_stats, const Workspace &w,
                            hipStream_t s);
+hipError_t launch_interact_backward(const sph_grid *g, const sph_params *p, const sph_state *st,
+                                    const sph_cells *cells, const float *ace_bar, float *pos_bar,
+                                    float *velrho_bar, double *alpha_bar, const Workspace &w,
+                                    hipStream_t s);
+hipError_t launch_unsort_adjoint(const int32_t *perm, int32_t n, const sph_adjoint *dst_bar,
+                                 sph_adjoint *src_bar, hipStream_t s);
 hipError_t launch_step(const sph_grid *g, const sph_params *p, sph_state *st, const float *ace,
                        const float *visc, double *dt, long long step, unsigned flags,
-                       const Workspace &w, int32_t *dev_status, hipStream_t s);
+                       sph_adjoint *adj, const Workspace &w, int32_t *dev_status, hipStream_t s);
 
 // ---------------------------------------------------------------------------
 // Device helpers

@@ -166,9 +166,86 @@ __global__ void k_verlet(StepConsts C, int32_t n, int32_t nb, int corrective,
     pos[i] = make_float4(on[0], on[1], on[2], pw);
 }
 
+
+// Transpose of k_verlet for a frozen time step (state arrays at level n, ace
+// the forward (a, D) of level n).  Adjoints in: x, (v, rho) of level n+1 and
+// of the stored level-n copy (velrho_prev_bar); out: the adjoint of (a, D)
+// and the level-n / level-(n-1) adjoints through the update.  A floored
+// boundary density blocks its adjoint; excluded slots pass through unchanged.
+__global__ void k_verlet_adj(StepConsts C, int32_t n, int32_t nb, int corrective,
+                             const double *__restrict__ dtp, const int32_t *__restrict__ cell,
+                             const float4 *__restrict__ velrho, const float4 *__restrict__ velrho_prev,
+                             const float4 *__restrict__ ace, float4 *__restrict__ pos_bar,
+                             float4 *__restrict__ velrho_bar, float4 *__restrict__ velrho_prev_bar,
+                             float4 *__restrict__ ace_bar)
+{
+    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    if (cell[i] == SPH_EXCLUDED) {
+        ace_bar[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+        return;
+    }
+    const double dt = dtp[0];
+    const float4 vb1 = velrho_bar[i];
+    const float4 pb1 = velrho_prev_bar[i];
+    double rbar1 = vb1.w;
+    if (i < nb && C.bound_floor) {
+        const double D = ace[i].w;
+        const double w1 = corrective ? (double)velrho[i].w + dt * D
+                                     : (double)velrho_prev[i].w + 2.0 * dt * D;
+        if (w1 < 0.0) rbar1 = 0.0;
+    }
+    const double Dbar = (corrective ? dt : 2.0 * dt) * rbar1;
+    const double rb_new = corrective ? (double)pb1.w + rbar1 : (double)pb1.w;
+    const double rpb_new = corrective ? 0.0 : rbar1;
+    if (i < nb) {
+        ace_bar[i] = make_float4(0.f, 0.f, 0.f, (float)Dbar);
+        velrho_bar[i].w = (float)rb_new;
+        velrho_prev_bar[i].w = (float)rpb_new;
+        return;
+    }
+    const float4 xb1 = pos_bar[i];
+    const double kv = corrective ? dt : 2.0 * dt;
+    const double h2 = 0.5 * dt * dt;
+    ace_bar[i] = make_float4((float)(h2 * xb1.x + kv * vb1.x), (float)(h2 * xb1.y + kv * vb1.y),
+                             (float)(h2 * xb1.z + kv * vb1.z), (float)Dbar);
+    const double cv = corrective ? 1.0 : 0.0;
+    velrho_bar[i] = make_float4((float)(dt * xb1.x + pb1.x + cv * vb1.x),
+                                (float)(dt * xb1.y + pb1.y + cv * vb1.y),
+                                (float)(dt * xb1.z + pb1.z + cv * vb1.z), (float)rb_new);
+    velrho_prev_bar[i] = corrective ? make_float4(0.f, 0.f, 0.f, (float)rpb_new)
+                                    : make_float4(vb1.x, vb1.y, vb1.z, (float)rpb_new);
+}
+
+// Transpose of the gather of sph_build_cells: src_bar[perm[i]] = dst_bar[i].
+__global__ void k_unsort(int32_t n, const int32_t *__restrict__ perm, const float4 *__restrict__ d0,
+                         const float4 *__restrict__ d1, const float4 *__restrict__ d2,
+                         float4 *__restrict__ s0, float4 *__restrict__ s1, float4 *__restrict__ s2)
+{
+    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int32_t j = min(max(perm[i], 0), n - 1);
+    s0[j] = d0[i];
+    s1[j] = d1[i];
+    s2[j] = d2[i];
+}
+
+hipError_t launch_unsort_adjoint(const int32_t *perm, int32_t n, const sph_adjoint *dst_bar,
+                                 sph_adjoint *src_bar, hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    k_unsort<<<(n + 255) / 256, 256, 0, s>>>(n, perm, (const float4 *)dst_bar->pos_bar,
+                                             (const float4 *)dst_bar->velrho_bar,
+                                             (const float4 *)dst_bar->velrho_prev_bar,
+                                             (float4 *)src_bar->pos_bar,
+                                             (float4 *)src_bar->velrho_bar,
+                                             (float4 *)src_bar->velrho_prev_bar);
+    return hipGetLastError();
+}
+
 hipError_t launch_step(const sph_grid *g, const sph_params *p, sph_state *st, const float *ace,
                        const float *visc, double *dt, long long step, unsigned flags,
-                       const Workspace &w, int32_t *dev_status, hipStream_t s)
+                       sph_adjoint *adj, const Workspace &w, int32_t *dev_status, hipStream_t s)
 {
     StepConsts C;
     for (int d = 0; d < 3; ++d) {
@@ -185,6 +262,15 @@ hipError_t launch_step(const sph_grid *g, const sph_params *p, sph_state *st, co
     C.verlet_ns = p->verlet_ns;
     C.bound_floor = p->bound_floor;
     const int32_t n = st->n, nb = st->nb;
+    const int corrective = step == 0 || ((step + 1) % p->verlet_ns) == 0;
+    if (flags & SPH_ADJOINT) {
+        if (n > 0)
+            k_verlet_adj<<<(n + 255) / 256, 256, 0, s>>>(
+                C, n, nb, corrective, dt, st->cell, (const float4 *)st->velrho,
+                (const float4 *)st->velrho_prev, (const float4 *)ace, (float4 *)adj->pos_bar,
+                (float4 *)adj->velrho_bar, (float4 *)adj->velrho_prev_bar, (float4 *)adj->ace_bar);
+        return hipGetLastError();
+    }
     if (!(flags & SPH_FIXED_DT)) {
         int nblk = (int)(((int64_t)n + kReduceThreads - 1) / kReduceThreads);
         if (nblk > kReduceBlocksMax) nblk = kReduceBlocksMax;
@@ -193,7 +279,6 @@ hipError_t launch_step(const sph_grid *g, const sph_params *p, sph_state *st, co
                                                       (const float4 *)ace, visc, w.reduce);
         k_cfl_final<<<1, kReduceThreads, 0, s>>>(C, nblk, w.reduce, dt, dev_status);
     }
-    const int corrective = step == 0 || ((step + 1) % p->verlet_ns) == 0;
     if (n > 0)
         k_verlet<<<(n + 255) / 256, 256, 0, s>>>(C, n, nb, corrective, dt, st->cell,
                                                  (float4 *)st->pos, (float4 *)st->velrho,

@@ -24,7 +24,8 @@ SPH_EXCLUDED = 2**31 - 1
 ABI_VERSION = 1
 
 EXPORTS = ["sph_workspace_bytes", "sph_abi_version", "sph_encode", "sph_decode",
-           "sph_build_cells", "sph_interact", "sph_step", "sph_interact_backward"]
+           "sph_build_cells", "sph_interact", "sph_step", "sph_interact_backward",
+           "sph_build_cells_backward"]
 
 
 class Grid(C.Structure):
@@ -85,8 +86,9 @@ def load(path: str = LIB_PATH):
                            P(Adjoint), vp, sz, vp, vp]
     L.sph_interact_backward.argtypes = [P(Grid), P(Params), P(State), P(Cells), vp, vp, vp, vp,
                                         vp, sz, vp]
+    L.sph_build_cells_backward.argtypes = [vp, C.c_int32, P(Adjoint), P(Adjoint), vp]
     for f in ["sph_encode", "sph_decode", "sph_build_cells", "sph_interact", "sph_step",
-              "sph_interact_backward"]:
+              "sph_interact_backward", "sph_build_cells_backward"]:
         getattr(L, f).restype = C.c_int
     if L.sph_abi_version() != ABI_VERSION:
         raise SphError("libsph.so ABI version mismatch")
@@ -146,6 +148,20 @@ def sph_step(grid, params, state, ace, visc, dt, step, flags, ws, dev_status, ad
     _check(load().sph_step(C.byref(grid), C.byref(params), C.byref(state), _ptr(ace), _ptr(visc),
                            _ptr(dt), int(step), int(flags), C.byref(adj) if adj else None,
                            _ptr(ws), ws.numel(), _ptr(dev_status), _stream(stream)), "sph_step")
+
+
+def sph_interact_backward(grid, params, state, cells, ace_bar, pos_bar, velrho_bar, alpha_bar,
+                          ws, stream=None):
+    _check(load().sph_interact_backward(C.byref(grid), C.byref(params), C.byref(state),
+                                        C.byref(cells), _ptr(ace_bar), _ptr(pos_bar),
+                                        _ptr(velrho_bar), _ptr(alpha_bar), _ptr(ws), ws.numel(),
+                                        _stream(stream)), "sph_interact_backward")
+
+
+def sph_build_cells_backward(perm, n, dst_bar, src_bar, stream=None):
+    _check(load().sph_build_cells_backward(_ptr(perm), int(n), C.byref(dst_bar),
+                                           C.byref(src_bar), _stream(stream)),
+           "sph_build_cells_backward")
 
 
 # ----------------------------------------------------------------------------
