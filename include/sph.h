@@ -82,6 +82,14 @@ typedef struct {
     int32_t nsub;     /* 1 (cell = support 2h) or 2 (cell = h)                       */
 } sph_grid;
 
+/* Smoothing kernels (Section 2: both have compact support q = r/h < 2).
+ *   SPH_WENDLAND5:    W = aD (1 - q/2)^4 (2q + 1),            aD = 21 / (16 pi h^3)
+ *   SPH_CUBIC_SPLINE: W = aD (1 - 3q^2/2 + 3q^3/4) for q < 1,
+ *                     W = aD (2 - q)^3 / 4 for 1 <= q < 2,     aD = 1 / (pi h^3)
+ *                     (the Table 1 kernel). */
+#define SPH_WENDLAND5 0
+#define SPH_CUBIC_SPLINE 1
+
 /* Physical constants (Table 1: Verlet, variable time step, Monaghan artificial
  * viscosity, Tait equation of state, dynamic boundaries). */
 typedef struct {
@@ -94,7 +102,7 @@ typedef struct {
     double g[3];     /* gravity, applied to fluid particles                      */
     double mass;     /* particle mass (fluid and boundary)                       */
     double cfl;      /* Courant factor of the variable time step                 */
-    int32_t kernel;  /* 0 = Wendland quintic (the only kernel built so far)      */
+    int32_t kernel;  /* SPH_WENDLAND5 or SPH_CUBIC_SPLINE                        */
     int32_t verlet_ns;   /* corrective Verlet step every verlet_ns steps (>= 1)  */
     int32_t bound_floor; /* 1: boundary density floored at rho0 after each step  */
     int32_t pad_;

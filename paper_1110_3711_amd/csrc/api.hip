@@ -29,7 +29,7 @@ bool params_ok(const sph_grid *g, const sph_params *p)
     if (!p) return false;
     if (!(p->h > 0.0) || !(p->rho0 > 0.0) || !(p->c0 > 0.0) || !(p->mass > 0.0)) return false;
     if (p->gamma != 7.0) return false;
-    if (p->kernel != 0) return false;
+    if (p->kernel != SPH_WENDLAND5 && p->kernel != SPH_CUBIC_SPLINE) return false;
     if (p->verlet_ns < 1) return false;
     if (!(p->eta2 > 0.0) || !(p->alpha >= 0.0) || !(p->cfl > 0.0)) return false;
     // the (2 nsub + 1)^3 stencil must cover the support 2h, with margin for

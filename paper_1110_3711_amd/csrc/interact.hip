@@ -32,8 +32,10 @@ constexpr int kRing = 128;           // per-wave ring of compacted candidates
 constexpr int kRingAlloc = kRing + kWave;  // + one trash slot per lane
 constexpr int kMaxRuns = 2 * 25;     // types x (2n+1)^2, n <= 2
 constexpr int kMaxRunCells = 5;      // 2n+1
-constexpr int kStageIters = kTile / kThreads;
 constexpr float kFar = 1.0e30f;      // padding position: never within the support
+constexpr int kXcds = 8;             // MI355X: workgroups are dealt to 8 XCDs round robin
+constexpr int kBinBits = 5;          // staged candidates are ordered by 32 bins of x
+constexpr int kBins = 1 << kBinBits;
 
 struct RunTable {
     int32_t nruns;
@@ -183,27 +185,33 @@ template <int KIND>
 struct KindTraits {
     static constexpr bool fluid = KIND == kFwdFluid || KIND == kBwdFluid;
     static constexpr bool bwd = KIND >= kBwdFluid;
-    static constexpr int tile = bwd ? 1536 : kTile;  // LDS: 32 B (forward) / 48 B per candidate
+    static constexpr int tile = bwd ? 1280 : kTile;  // LDS: 32 B (forward) / 48 B per candidate
 };
 
-template <int KIND, bool STATS>
+template <int KIND, bool STATS, int KER>
 __global__ __launch_bounds__(kThreads) void k_interact(PairConsts K, PairArgs A)
 {
     using T = KindTraits<KIND>;
     constexpr bool FLUID = T::fluid;
     constexpr bool BWD = T::bwd;
     constexpr int TILE = T::tile;
-    constexpr int STAGE = TILE / kThreads;
-    __shared__ float4 sP[TILE];                   // (offset in target frame, P/rho^2)
+    constexpr int STAGE = (TILE + kThreads - 1) / kThreads;
+    __shared__ float4 sP[TILE + 2 * kWave];       // (offset in target frame, P/rho^2) + padding
     __shared__ float4 sV[TILE];                   // (v, rho - rho0)
     __shared__ float4 sA[BWD ? TILE : 1];         // backward: (abar, Dbar), abar = 0 on boundary
     __shared__ uint16_t sRing[kWaves][kRingAlloc];
+    __shared__ uint16_t sMap[TILE];               // staging index -> sorted slot
+    __shared__ uint16_t sCnt[STAGE][kWaves][kBins];
+    __shared__ int32_t sBin[kBins + 1];           // first sorted slot of each x-bin
     __shared__ int32_t sSlot[STATS ? TILE : 1];   // candidate slot (diagnostics only)
     __shared__ RunTable R;
     __shared__ int32_t sItem;
 
+    auto xbin = [&](float x) { return min(max((int)((x - K.xlo) * K.xscale), 0), kBins - 1); };
+
     const int lane = threadIdx.x & (kWave - 1);
     const int wave = threadIdx.x / kWave;
+    const int trash = kRing + lane;  // per-lane ring slot for rejected candidates
     // Work items: fluid cells are list[info[0] .. info[0] + info[1]); boundary
     // cells with fluid in reach are active[0 .. nactive).  Counts are clamped
     // so that inconsistent inputs can never index outside [0, n).
@@ -216,12 +224,33 @@ __global__ __launch_bounds__(kThreads) void k_interact(PairConsts K, PairArgs A)
         nitems = min(max(A.counts[0], 0), K.n);
     }
     unsigned long long pairs_acc = 0;  // wave-uniform
+    // XCD-aware dynamic schedule: the work list is cut into kXcds contiguous
+    // chunks with one counter each; workgroup b starts on chunk b mod kXcds
+    // (the XCD it runs on), so neighbouring cells share that XCD's L2, and
+    // moves to the next chunk when one is exhausted.  Every workgroup gives up
+    // after kXcds exhausted chunks, so the grid always drains.
+    const int home = blockIdx.x % kXcds;
+    int tries = 0;  // meaningful in thread 0 only
 
     for (;;) {
-        if (threadIdx.x == 0) sItem = atomicAdd(A.queue, 1);
+        if (threadIdx.x == 0) {
+            int32_t it = -1;
+            while (tries < kXcds) {
+                const int x = (home + tries) % kXcds;
+                const int32_t lo = (int32_t)(((int64_t)nitems * x) / kXcds);
+                const int32_t hi = (int32_t)(((int64_t)nitems * (x + 1)) / kXcds);
+                const int32_t k = atomicAdd(A.queue + x, 1);
+                if (k < hi - lo) {
+                    it = lo + k;
+                    break;
+                }
+                ++tries;
+            }
+            sItem = it;
+        }
         __syncthreads();
         const int32_t item = sItem;
-        if (item >= nitems) break;
+        if (item < 0) break;
         const int32_t key = min(max(A.items[ibase + item], 0), 2 * K.ncell - 1);
         const int32_t c = FLUID ? max(key - K.ncell, 0) : min(key, K.ncell - 1);
         const int32_t cx = c % K.nc0, cy = (c / K.nc0) % K.nc1, cz = c / (K.nc0 * K.nc1);
@@ -235,43 +264,117 @@ __global__ __launch_bounds__(kThreads) void k_interact(PairConsts K, PairArgs A)
 
         for (int32_t tb = 0; tb < max(total, 1); tb += TILE) {
             const int32_t tlen = max(min(TILE, total - tb), 0);
-            const int32_t tpad = (tlen + kWave - 1) & ~(kWave - 1);
-            // ---- stage candidates [tb, tb + tlen) into LDS; pad to a multiple of 64
-#pragma unroll
-            for (int u = 0; u < STAGE; ++u) {
-                const int32_t l = threadIdx.x + u * kThreads;
-                if (l < tlen) {
-                    const int32_t v = tb + l;
-                    int lo = 0, hi = nr;  // find r with vstart[r] <= v < vstart[r+1]
-                    while (hi - lo > 1) {
-                        const int mid = (lo + hi) >> 1;
-                        if (R.vstart[mid] <= v) lo = mid;
-                        else hi = mid;
-                    }
-                    const int32_t j = min(max(R.s[lo][0] + (v - R.vstart[lo]), 0), K.n - 1);
-                    int ci = 0;
-                    for (int i = 1; i < R.ncx[lo]; ++i) ci += R.s[lo][i] <= j ? 1 : 0;
-                    const float sx = (float)(R.dx0[lo] + ci) * K.cellf;  // (k_b - k_a) cell, exact
-                    const float4 p = A.pos[j];
-                    sP[l] = make_float4(p.x + sx, p.y + R.sy[lo], p.z + R.sz[lo], p.w);
-                    sV[l] = A.velrho[j];
-                    if (BWD) {
-                        float4 ab = A.ace[j];
-                        if (lo < nbruns) ab.x = ab.y = ab.z = 0.f;
-                        sA[l] = ab;
-                    }
-                    if (STATS) sSlot[l] = j;
-                } else if (l < tpad) {
-                    sP[l] = make_float4(kFar, kFar, kFar, 0.f);
+            // ---- stage candidates [tb, tb + tlen) into LDS, ordered by the x-bin of
+            //      their position in the target frame (stable in staging order), so
+            //      that each target scans one contiguous window |x_a - x_b| < 2h
+            // locate staging index l: slot j of the sorted state and its run
+            auto locate = [&](int32_t l, int32_t &j, int &run) {
+                const int32_t v = tb + min(l, max(tlen - 1, 0));
+                int lo = 0, hi = nr;  // find r with vstart[r] <= v < vstart[r+1]
+                while (hi - lo > 1) {
+                    const int mid = (lo + hi) >> 1;
+                    if (R.vstart[mid] <= v) lo = mid;
+                    else hi = mid;
                 }
+                j = min(max(R.s[lo][0] + (v - R.vstart[lo]), 0), K.n - 1);
+                run = lo;
+            };
+            // frame shift (k_b - k_a) cell along x, exact
+            auto shift_x = [&](int32_t j, int run) {
+                int ci = 0;
+                for (int i = 1; i < R.ncx[run]; ++i) ci += R.s[run][i] <= j ? 1 : 0;
+                return (float)(R.dx0[run] + ci) * K.cellf;
+            };
+            // rank among the equal x-bins of this wave (stable in lane order)
+            auto rank_round = [&](int u, int bin) {
+                const bool valid = (int32_t)(threadIdx.x + u * kThreads) < tlen;
+                unsigned long long peers = ballot(valid);
+                for (int b = 0; b < kBinBits; ++b) {
+                    const bool bit = (bin >> b) & 1;
+                    const unsigned long long mb = ballot(bit);
+                    peers &= bit ? mb : ~mb;
+                }
+                const int rk = (int)lane_rank(peers);
+                if (valid && rk == 0) sCnt[u][wave][bin] = (uint16_t)__popcll(peers);
+                return rk;
+            };
+            static_assert(STAGE <= 4, "staging rounds");
+            for (int i = threadIdx.x; i < STAGE * kWaves * kBins; i += kThreads)
+                (&sCnt[0][0][0])[i] = 0;
+            // pass A: locate all of this thread's candidates, then one round of loads
+            int32_t j0 = 0, j1 = 0, j2 = 0, j3 = 0;
+            int q0 = 0, q1 = 0, q2 = 0, q3 = 0;
+            locate(threadIdx.x, j0, q0);
+            if (STAGE > 1) locate(threadIdx.x + kThreads, j1, q1);
+            if (STAGE > 2) locate(threadIdx.x + 2 * kThreads, j2, q2);
+            if (STAGE > 3) locate(threadIdx.x + 3 * kThreads, j3, q3);
+            const float x0 = A.pos[j0].x, x1 = STAGE > 1 ? A.pos[j1].x : 0.f,
+                        x2 = STAGE > 2 ? A.pos[j2].x : 0.f, x3 = STAGE > 3 ? A.pos[j3].x : 0.f;
+            const int bn0 = xbin(x0 + shift_x(j0, q0));
+            const int bn1 = STAGE > 1 ? xbin(x1 + shift_x(j1, q1)) : 0;
+            const int bn2 = STAGE > 2 ? xbin(x2 + shift_x(j2, q2)) : 0;
+            const int bn3 = STAGE > 3 ? xbin(x3 + shift_x(j3, q3)) : 0;
+            __syncthreads();
+            const int rk0 = rank_round(0, bn0);
+            const int rk1 = STAGE > 1 ? rank_round(1, bn1) : 0;
+            const int rk2 = STAGE > 2 ? rank_round(2, bn2) : 0;
+            const int rk3 = STAGE > 3 ? rank_round(3, bn3) : 0;
+            __syncthreads();
+            if ((int)threadIdx.x < kBins) {  // per-bin offsets over (round, wave)
+                const int b = threadIdx.x;
+                int run = 0;
+                for (int u = 0; u < STAGE; ++u)
+                    for (int w = 0; w < kWaves; ++w) {
+                        const int cc = sCnt[u][w][b];
+                        sCnt[u][w][b] = (uint16_t)run;
+                        run += cc;
+                    }
+                sBin[b + 1] = run;
             }
+            __syncthreads();
+            if (threadIdx.x < kWave) {  // bin starts: exclusive scan of the bin totals
+                const int ln = threadIdx.x;
+                int32_t v = ln < kBins ? sBin[ln + 1] : 0;
+                for (int o = 1; o < kWave; o <<= 1) {
+                    const int32_t t = __shfl_up(v, o);
+                    if (ln >= o) v += t;
+                }
+                if (ln < kBins) sBin[ln + 1] = v;
+                if (ln == 0) sBin[0] = 0;
+            }
+            __syncthreads();
+            // pass B: write each candidate to its sorted slot
+            auto place = [&](int u, int32_t j, int run, int bin, int rk) {
+                const int32_t l = threadIdx.x + u * kThreads;
+                if (l >= tlen) return;
+                const int slot = sBin[bin] + sCnt[u][wave][bin] + rk;
+                float4 pp = A.pos[j];
+                pp.x += shift_x(j, run);
+                pp.y += R.sy[run];
+                pp.z += R.sz[run];
+                sP[slot] = pp;
+                sV[slot] = A.velrho[j];
+                if (BWD) {
+                    float4 ab = A.ace[j];
+                    if (run < nbruns) ab.x = ab.y = ab.z = 0.f;
+                    sA[slot] = ab;
+                }
+                if (STATS) sSlot[slot] = j;
+                sMap[l] = (uint16_t)slot;
+            };
+            place(0, j0, q0, bn0, rk0);
+            if (STAGE > 1) place(1, j1, q1, bn1, rk1);
+            if (STAGE > 2) place(2, j2, q2, bn2, rk2);
+            if (STAGE > 3) place(3, j3, q3, bn3, rk3);
+            if (threadIdx.x < 2 * kWave) sP[tlen + threadIdx.x] = make_float4(kFar, kFar, kFar, 0.f);
             __syncthreads();
 
             // ---- one wavefront per target
             const int32_t selfbase = FLUID ? R.vstart[R.self_run] - R.s[R.self_run][0] - tb : 0;
             for (int32_t a = tbeg + wave; a < tend; a += kWaves) {
-                const int32_t self_l = FLUID ? selfbase + a : -1;
-                const bool self_here = FLUID && self_l >= 0 && self_l < tlen;
+                const int32_t self_v = FLUID ? selfbase + a : -1;  // staging index of a
+                const bool self_here = FLUID && self_v >= 0 && self_v < tlen;
+                const int32_t self_l = self_here ? (int32_t)sMap[self_v] : -1;
                 float4 pa, va, aa = make_float4(0.f, 0.f, 0.f, 0.f);
                 if (self_here) {
                     pa = sP[self_l];
@@ -307,8 +410,17 @@ __global__ __launch_bounds__(kThreads) void k_interact(PairConsts K, PairArgs A)
                     const float rx = pa.x - pb.x, ry = pa.y - pb.y, rz = pa.z - pb.z;
                     const float r2 = __builtin_fmaf(rz, rz, __builtin_fmaf(ry, ry, rx * rx));
                     const float r = __builtin_amdgcn_sqrtf(r2);
-                    const float wq = __builtin_fmaf(-0.5f * K.inv_h, r, 1.0f);
-                    const float F = K.kf * (wq * wq * wq);
+                    // kernel gradient factor F (grad_a W = F r_ab)
+                    float F, wq = 0.f, qq = 0.f;
+                    if (KER == SPH_WENDLAND5) {
+                        wq = __builtin_fmaf(-0.5f * K.inv_h, r, 1.0f);
+                        F = K.kf * (wq * wq * wq);
+                    } else {
+                        qq = r * K.inv_h;
+                        const float t = 2.f - qq;
+                        F = qq < 1.f ? K.kc_in * __builtin_fmaf(2.25f, qq, -3.f)
+                                     : K.kc_out * (t * t) * __builtin_amdgcn_rcpf(r);
+                    }
                     const float vx = va.x - vb.x, vy = va.y - vb.y, vz = va.z - vb.z;
                     const float vdr = __builtin_fmaf(vz, rz, __builtin_fmaf(vy, ry, vx * rx));
                     if (!BWD) {
@@ -344,9 +456,16 @@ __global__ __launch_bounds__(kThreads) void k_interact(PairConsts K, PairArgs A)
                         const float dpi_dra = K.kpi * K.inv_rho0 * __builtin_fmaf(2.f, ta, -tb) * mneg;
                         s3 = __builtin_fmaf(-F * Q, dpa + dpi_dra, s3);
                         if (FLUID) {
-                            // dF/dr / r = -(3 kf / 2h) wq^2 / r; 0 for the self pair
-                            const float Fr = r2 > 0.f ? K.kfr * wq * wq * __builtin_amdgcn_rcpf(r)
-                                                      : 0.f;
+                            // (dF/dr) / r; 0 for the self pair
+                            float Fr;
+                            if (KER == SPH_WENDLAND5) {
+                                Fr = K.kfr * wq * wq * __builtin_amdgcn_rcpf(r);
+                            } else {
+                                const float ir = __builtin_amdgcn_rcpf(r);
+                                Fr = qq < 1.f ? K.kcr_in * ir
+                                              : K.kcr_out * __builtin_fmaf(-qq, qq, 4.f) * (ir * ir * ir);
+                            }
+                            Fr = r2 > 0.f ? Fr : 0.f;
                             // continuity
                             const float sD = aa.w + ab.w;
                             const float c1 = sD * F, c2 = sD * vdr * Fr;
@@ -379,7 +498,11 @@ __global__ __launch_bounds__(kThreads) void k_interact(PairConsts K, PairArgs A)
                     const float r2 = __builtin_fmaf(rz, rz, __builtin_fmaf(ry, ry, rx * rx));
                     const bool pass = r2 < K.rc2;
                     const unsigned long long m = ballot(pass);
-                    const int slot = pass ? ((wp + (int)lane_rank(m)) & (kRing - 1)) : kRing + lane;
+                    // rank in every lane (no exec-mask switch), then the trash slot
+                    // for the lanes that failed
+                    int rk = (int)lane_rank(m);
+                    asm volatile("" : "+v"(rk));
+                    const int slot = pass ? ((wp + rk) & (kRing - 1)) : trash;
                     sRing[wave][slot] = (uint16_t)(cb0 + lane);
                     wp += __popcll(m);
                     if (wp - rp >= kWave) {
@@ -388,19 +511,21 @@ __global__ __launch_bounds__(kThreads) void k_interact(PairConsts K, PairArgs A)
                         rp += kWave;
                     }
                 };
-                // two chunks per iteration, each prefetched one chunk ahead
-                float4 p0 = sP[lane];
-                float4 p1 = tpad > kWave ? sP[kWave + lane] : p0;
-                int32_t cb0 = 0;
-                for (; cb0 + 2 * kWave <= tpad; cb0 += 2 * kWave) {
-                    const float4 c0 = p0;
-                    if (cb0 + 2 * kWave < tpad) p0 = sP[cb0 + 2 * kWave + lane];
+                // the window of x-bins within 2h of the target (conservative: bins
+                // are monotone in x), rounded up to whole chunks of 64; entries past
+                // the window are real candidates or padding and are tested as usual.
+                // Two chunks per iteration, both loaded up front: the second read
+                // ends before tlen + 2 * kWave, inside the padding.
+                // (wave-uniform: every lane holds the same target)
+                const int32_t w0 = __builtin_amdgcn_readfirstlane(sBin[xbin(pa.x - K.xwin)]);
+                const int32_t w1 = __builtin_amdgcn_readfirstlane(sBin[xbin(pa.x + K.xwin) + 1]);
+                const int32_t wend = w0 + ((w1 - w0 + kWave - 1) & ~(kWave - 1));
+                for (int32_t cb0 = w0; cb0 < wend; cb0 += 2 * kWave) {
+                    const float4 c0 = sP[cb0 + lane];
+                    const float4 c1 = sP[cb0 + kWave + lane];
                     chunk(c0, cb0);
-                    const float4 c1 = p1;
-                    if (cb0 + 3 * kWave < tpad) p1 = sP[cb0 + 3 * kWave + lane];
-                    chunk(c1, cb0 + kWave);
+                    if (cb0 + kWave < wend) chunk(c1, cb0 + kWave);
                 }
-                if (cb0 < tpad) chunk(p0, cb0);
                 if (wp > rp) {
                     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
                     if (lane < wp - rp) pair(sRing[wave][(rp + lane) & (kRing - 1)]);
@@ -550,6 +675,12 @@ static PairConsts pair_consts(const sph_grid *g, const sph_params *p, int32_t n)
     K.kpi = (float)(-p->alpha * p->c0 / p->rho0);
     K.kpa = (float)(-p->c0 / p->rho0);
     K.kfr = (float)(1.5 * 5.0 * ad / (h * h * h));
+    const double ac = 1.0 / (pi * h * h * h);
+    K.kc_in = (float)(ac / (h * h));
+    K.kc_out = (float)(-0.75 * ac / h);
+    K.kcr_in = (float)(2.25 * ac / (h * h * h));
+    K.kcr_out = (float)(0.75 * ac / h);
+    K.kernel = p->kernel;
     K.c0 = (float)p->c0;
     K.rho0 = (float)p->rho0;
     K.inv_rho0 = (float)(1.0 / p->rho0);
@@ -563,10 +694,14 @@ static PairConsts pair_consts(const sph_grid *g, const sph_params *p, int32_t n)
     K.nc2 = g->nc[2];
     K.ncell = (int32_t)ncell_of(g);
     K.n = n;
+    // x-bins over the staged extent [-(n + 1/2) cell, (n + 1/2) cell] of the target frame
+    K.xlo = (float)(-(g->nsub + 0.5) * g->cell);
+    K.xscale = (float)(kBins / ((2 * g->nsub + 1) * g->cell));
+    K.xwin = (float)(2.0 * h * (1.0 + 1.0 / 1024.0));
     return K;
 }
 
-template <int KIND, bool STATS>
+template <int KIND, bool STATS, int KER>
 static hipError_t launch_one(const PairConsts &K, const PairArgs &A, hipStream_t s)
 {
     int dev = 0, cus = 0, occ = 0;
@@ -574,12 +709,25 @@ static hipError_t launch_one(const PairConsts &K, const PairArgs &A, hipStream_t
     if (e != hipSuccess) return e;
     e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     if (e != hipSuccess) return e;
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_interact<KIND, STATS>, kThreads, 0);
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_interact<KIND, STATS, KER>, kThreads, 0);
     if (e != hipSuccess) return e;
     if (cus <= 0) cus = 1;
     if (occ <= 0) occ = 1;
-    k_interact<KIND, STATS><<<cus * occ, kThreads, 0, s>>>(K, A);
+    k_interact<KIND, STATS, KER><<<cus * occ, kThreads, 0, s>>>(K, A);
     return hipGetLastError();
+}
+
+// instantiation for the kernel shape; per-pair statistics only in the forward
+template <int KIND>
+static hipError_t launch_kind(const PairConsts &K, const PairArgs &A, bool stats, hipStream_t s)
+{
+    constexpr bool fwd = KIND == kFwdFluid || KIND == kFwdBound;
+    if (K.kernel == SPH_CUBIC_SPLINE) {
+        if (fwd && stats) return launch_one<KIND, fwd, SPH_CUBIC_SPLINE>(K, A, s);
+        return launch_one<KIND, false, SPH_CUBIC_SPLINE>(K, A, s);
+    }
+    if (fwd && stats) return launch_one<KIND, fwd, SPH_WENDLAND5>(K, A, s);
+    return launch_one<KIND, false, SPH_WENDLAND5>(K, A, s);
 }
 
 static PairArgs base_args(const sph_state *st, const sph_cells *cells)
@@ -614,23 +762,23 @@ hipError_t launch_interact(const sph_grid *g, const sph_params *p, const sph_sta
     A.visc = visc;
     A.npairs = npairs;
     A.stats = nbr_stats;
-    // counters: [0] fluid queue, [1] boundary queue, [2] active boundary cells
+    // counters: [0, 8) fluid queues, [8, 16) boundary queues, [16] active boundary cells
     hipError_t e = hipSuccess;
     if (parts & SPH_PI_FLUID) {
-        k_zero_counters<<<1, 64, 0, s>>>(w.counters + 0, 1);
+        k_zero_counters<<<1, 64, 0, s>>>(w.counters + 0, kXcds);
         A.queue = w.counters + 0;
-        e = nbr_stats ? launch_one<kFwdFluid, true>(K, A, s) : launch_one<kFwdFluid, false>(K, A, s);
+        e = launch_kind<kFwdFluid>(K, A, nbr_stats != nullptr, s);
         if (e != hipSuccess) return e;
     }
     if (parts & SPH_PI_BOUNDARY) {
-        k_zero_counters<<<1, 64, 0, s>>>(w.counters + 1, 2);
+        k_zero_counters<<<1, 64, 0, s>>>(w.counters + 8, kXcds + 1);
         k_zero_excluded<<<64, 256, 0, s>>>(st->n, cells->info, (float4 *)ace, visc, nbr_stats);
         k_bound_filter<<<256, 256, 0, s>>>(K, cells->start, cells->list, cells->info, w.active,
-                                           w.counters + 2, (float4 *)ace, visc, nbr_stats);
+                                           w.counters + 16, (float4 *)ace, visc, nbr_stats);
         A.items = w.active;
-        A.counts = w.counters + 2;
-        A.queue = w.counters + 1;
-        e = nbr_stats ? launch_one<kFwdBound, true>(K, A, s) : launch_one<kFwdBound, false>(K, A, s);
+        A.counts = w.counters + 16;
+        A.queue = w.counters + 8;
+        e = launch_kind<kFwdBound>(K, A, nbr_stats != nullptr, s);
     }
     return e;
 }
@@ -683,17 +831,18 @@ hipError_t launch_interact_backward(const sph_grid *g, const sph_params *p, cons
     A.xbar = (float4 *)pos_bar;
     A.vbar = (float4 *)velrho_bar;
     A.alpha_part = w.alpha_part;
-    k_zero_counters<<<1, 64, 0, s>>>(w.counters + 3, 3);
-    A.queue = w.counters + 3;
-    hipError_t e = launch_one<kBwdFluid, false>(K, A, s);
+    // counters: [24, 32) fluid queues, [32, 40) boundary queues, [40] active cells
+    k_zero_counters<<<1, 64, 0, s>>>(w.counters + 24, 2 * kXcds + 1);
+    A.queue = w.counters + 24;
+    hipError_t e = launch_kind<kBwdFluid>(K, A, false, s);
     if (e != hipSuccess) return e;
     // boundary gatherers: only cells with fluid in reach have non-zero terms
     k_bound_filter<<<256, 256, 0, s>>>(K, cells->start, cells->list, cells->info, w.active,
-                                       w.counters + 5, nullptr, nullptr, nullptr);
+                                       w.counters + 40, nullptr, nullptr, nullptr);
     A.items = w.active;
-    A.counts = w.counters + 5;
-    A.queue = w.counters + 4;
-    e = launch_one<kBwdBound, false>(K, A, s);
+    A.counts = w.counters + 40;
+    A.queue = w.counters + 32;
+    e = launch_kind<kBwdBound>(K, A, false, s);
     if (e != hipSuccess) return e;
     int nblk = (int)(((int64_t)st->n + kReduceThreads - 1) / kReduceThreads);
     if (nblk > kReduceBlocksMax) nblk = kReduceBlocksMax;

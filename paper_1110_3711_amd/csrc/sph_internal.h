@@ -33,7 +33,7 @@ struct Workspace {
     uint32_t *hist;                           // [kRadix * nblk_sort]
     unsigned long long *partials;             // scan partial sums
     unsigned long long *keyscan;              // [nkeys + 1] packed (count << 32 | nonempty)
-    int32_t *counters;                        // [16] work queues and flags
+    int32_t *counters;                        // [64] work queues and flags
     int32_t *active;                          // [n] boundary cells with fluid in reach
     float *alpha_part;                        // [n] per-slot alpha adjoint
     double *reduce;                           // [3 * kReduceBlocksMax] CFL partials
@@ -65,7 +65,7 @@ inline bool layout_workspace(const sph_grid *g, int64_t n, void *base, Workspace
     if (np2 > np) np = np2;
     const size_t o_p = take(sizeof(unsigned long long) * np);
     const size_t o_ks = take(sizeof(unsigned long long) * (size_t)(nkeys + 1));
-    const size_t o_c = take(sizeof(int32_t) * 16);
+    const size_t o_c = take(sizeof(int32_t) * 64);
     const size_t o_a = take(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
     const size_t o_ap = take(sizeof(float) * (size_t)(n > 0 ? n : 1));
     const size_t o_r = take(sizeof(double) * 3 * kReduceBlocksMax);
@@ -98,6 +98,14 @@ struct PairConsts {
     float kpi;       // -alpha c0 / rho0
     float kpa;       // -c0 / rho0 (d Pi / d alpha per unit cr min(mu, 0))
     float kfr;       // (dF/dr)/r = kfr (1 - q/2)^2 / r, kfr = -3 kf / (2h)
+    // cubic spline, aD = 1 / (pi h^3):
+    //   q < 1:  F = kc_in (9q/4 - 3),      (dF/dr)/r = kcr_in / r
+    //   q >= 1: F = kc_out (2 - q)^2 / r,  (dF/dr)/r = kcr_out (4 - q^2) / r^3
+    float kc_in;     // aD / h^2
+    float kc_out;    // -3 aD / (4h)
+    float kcr_in;    // 9 aD / (4 h^3)
+    float kcr_out;   // 3 aD / (4h)
+    int32_t kernel;  // SPH_WENDLAND5 or SPH_CUBIC_SPLINE (selects the instantiation)
     float c0;
     float rho0;
     float inv_rho0;
@@ -107,6 +115,7 @@ struct PairConsts {
     int32_t nc0, nc1, nc2;
     int32_t ncell;
     int32_t n;       // particles in the state
+    float xlo, xscale, xwin;  // x-bins of the staged candidates; window half-width
 };
 
 // Host launchers (one per source file).
