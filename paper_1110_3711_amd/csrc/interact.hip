@@ -29,7 +29,6 @@ constexpr int kThreads = 512;
 constexpr int kWaves = kThreads / kWave;
 constexpr int kTile = 2048;          // candidates staged per pass (multiple of 64)
 constexpr int kRing = 128;           // per-wave ring of compacted candidates
-constexpr int kRingAlloc = kRing + kWave;  // + one trash slot per lane
 constexpr int kMaxRuns = 2 * 25;     // types x (2n+1)^2, n <= 2
 constexpr int kMaxRunCells = 5;      // 2n+1
 constexpr float kFar = 1.0e30f;      // padding position: never within the support
@@ -102,6 +101,95 @@ __device__ inline unsigned wave_sum_u(unsigned v)
            (unsigned)__builtin_amdgcn_readlane((int)v, 16) +
            (unsigned)__builtin_amdgcn_readlane((int)v, 32) +
            (unsigned)__builtin_amdgcn_readlane((int)v, 48);
+}
+
+// one exchange step of a transposed reduction: lanes with the bit clear keep lo
+// and add the partner's lo, lanes with the bit set keep hi and add the
+// partner's hi, so the number of live values halves while each covers twice
+// the lanes
+template <int CTRL>
+__device__ inline float xchg(float lo, float hi, bool bit)
+{
+    return (bit ? hi : lo) + dpp_f<CTRL>(bit ? lo : hi);
+}
+
+// Cross-row steps use ds_bpermute with the byte addresses of lanes l ^ 16 and
+// l ^ 32 (computed once per thread).
+struct XorAddr {
+    int x16, x32;
+};
+
+__device__ inline XorAddr xor_addr(int lane)
+{
+    return XorAddr{(lane ^ 16) << 2, (lane ^ 32) << 2};
+}
+
+__device__ inline float bperm_f(int addr, float v)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_ds_bpermute(addr, __builtin_bit_cast(int, v)));
+}
+
+// row_ror:4 = 0x124, row_ror:8 = 0x128 (rotations keep lane & 3)
+// Sums of four per-lane values over the wave: lane l ends with the total of
+// value (l & 3).
+__device__ inline float wave_sum4(float v0, float v1, float v2, float v3, int lane, XorAddr xa)
+{
+    const bool b0 = lane & 1, b1 = lane & 2;
+    const float x = xchg<0xB1>(v0, v1, b0);
+    const float y = xchg<0xB1>(v2, v3, b0);
+    float z = xchg<0x4E>(x, y, b1);
+    z += dpp_f<0x124>(z);
+    z += dpp_f<0x128>(z);
+    z += bperm_f(xa.x16, z);
+    z += bperm_f(xa.x32, z);
+    return z;
+}
+
+// Sums of eight per-lane values: lane l ends with the total of value (l & 7).
+// The third exchange pairs quads q and q + 1 (mod 4) of a row by rotation;
+// with the row_ror:8 step after it every quad sum is counted once.
+__device__ inline float wave_sum8(float v0, float v1, float v2, float v3, float v4, float v5,
+                                  float v6, float v7, int lane, XorAddr xa)
+{
+    const bool b0 = lane & 1, b1 = lane & 2, b2 = lane & 4;
+    const float x0 = xchg<0xB1>(v0, v1, b0), x1 = xchg<0xB1>(v2, v3, b0);
+    const float x2 = xchg<0xB1>(v4, v5, b0), x3 = xchg<0xB1>(v6, v7, b0);
+    const float y0 = xchg<0x4E>(x0, x1, b1), y1 = xchg<0x4E>(x2, x3, b1);
+    float z = xchg<0x124>(y0, y1, b2);
+    z += dpp_f<0x128>(z);
+    z += bperm_f(xa.x16, z);
+    z += bperm_f(xa.x32, z);
+    return z;
+}
+
+// maximum of non-negative floats over the wave (their bit patterns order as
+// unsigned integers), in every lane
+__device__ inline float wave_max_nonneg(float f, XorAddr xa)
+{
+    unsigned v = __builtin_bit_cast(unsigned, f);
+    v = max(v, (unsigned)dpp_i<0xB1>((int)v));
+    v = max(v, (unsigned)dpp_i<0x4E>((int)v));
+    v = max(v, (unsigned)dpp_i<0x124>((int)v));
+    v = max(v, (unsigned)dpp_i<0x128>((int)v));
+    v = max(v, (unsigned)__builtin_amdgcn_ds_bpermute(xa.x16, (int)v));
+    v = max(v, (unsigned)__builtin_amdgcn_ds_bpermute(xa.x32, (int)v));
+    return __builtin_bit_cast(float, v);
+}
+
+// LDS byte addressing
+typedef __attribute__((address_space(3))) uint16_t lds_u16;
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(3))) f32x4 lds_f32x4;
+
+__device__ inline float4 lds_load4(uint32_t addr)
+{
+    const f32x4 v = *(const lds_f32x4 *)(uintptr_t)addr;
+    return make_float4(v.x, v.y, v.z, v.w);
+}
+
+__device__ inline uint32_t lds_addr(const void *p)
+{
+    return (uint32_t)(uintptr_t)(const __attribute__((address_space(3))) char *)p;
 }
 
 // ---------------------------------------------------------------------------
@@ -199,7 +287,8 @@ __global__ __launch_bounds__(kThreads) void k_interact(PairConsts K, PairArgs A)
     __shared__ float4 sP[TILE + 2 * kWave];       // (offset in target frame, P/rho^2) + padding
     __shared__ float4 sV[TILE];                   // (v, rho - rho0)
     __shared__ float4 sA[BWD ? TILE : 1];         // backward: (abar, Dbar), abar = 0 on boundary
-    __shared__ uint16_t sRing[kWaves][kRingAlloc];
+    __shared__ __align__(256) uint16_t sRing[kWaves][kRing];  // 256 bytes per wave
+    __shared__ uint16_t sTrash[kWaves][kWave];                // rejected candidates land here
     __shared__ uint16_t sMap[TILE];               // staging index -> sorted slot
     __shared__ uint16_t sCnt[STAGE][kWaves][kBins];
     __shared__ int32_t sBin[kBins + 1];           // first sorted slot of each x-bin
@@ -210,8 +299,17 @@ __global__ __launch_bounds__(kThreads) void k_interact(PairConsts K, PairArgs A)
     auto xbin = [&](float x) { return min(max((int)((x - K.xlo) * K.xscale), 0), kBins - 1); };
 
     const int lane = threadIdx.x & (kWave - 1);
-    const int wave = threadIdx.x / kWave;
-    const int trash = kRing + lane;  // per-lane ring slot for rejected candidates
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    // LDS byte addresses: ring of this wave (256-aligned), its first read entry
+    // per lane, this lane's trash slot, and the staged arrays
+    uint32_t rbase = lds_addr(&sRing[wave][0]);
+    const uint32_t rfirst = rbase | (2u * lane);
+    asm volatile("" : "+v"(rbase));  // per-lane copy: one and-or per ring slot
+    const XorAddr xa = xor_addr(lane);
+    uint32_t lane16 = (uint32_t)lane << 4;  // byte offset of this lane's entry in a chunk
+    asm volatile("" : "+v"(lane16));
+    const uint32_t taddr = lds_addr(&sTrash[wave][lane]);
+    const uint32_t sPb = lds_addr(sP), sVb = lds_addr(sV), sAb = lds_addr(sA);
     // Work items: fluid cells are list[info[0] .. info[0] + info[1]); boundary
     // cells with fluid in reach are active[0 .. nactive).  Counts are clamped
     // so that inconsistent inputs can never index outside [0, n).
@@ -249,17 +347,18 @@ __global__ __launch_bounds__(kThreads) void k_interact(PairConsts K, PairArgs A)
             sItem = it;
         }
         __syncthreads();
-        const int32_t item = sItem;
+        const int32_t item = __builtin_amdgcn_readfirstlane(sItem);
         if (item < 0) break;
-        const int32_t key = min(max(A.items[ibase + item], 0), 2 * K.ncell - 1);
+        const int32_t key =
+            __builtin_amdgcn_readfirstlane(min(max(A.items[ibase + item], 0), 2 * K.ncell - 1));
         const int32_t c = FLUID ? max(key - K.ncell, 0) : min(key, K.ncell - 1);
         const int32_t cx = c % K.nc0, cy = (c / K.nc0) % K.nc1, cz = c / (K.nc0 * K.nc1);
-        const int32_t tbeg = min(max(A.start[key], 0), K.n);
-        const int32_t tend = min(max(A.start[key + 1], tbeg), K.n);
+        const int32_t tbeg = __builtin_amdgcn_readfirstlane(min(max(A.start[key], 0), K.n));
+        const int32_t tend = __builtin_amdgcn_readfirstlane(min(max(A.start[key + 1], tbeg), K.n));
 
         build_runs<FLUID>(K, A.start, cx, cy, cz, R);
-        const int32_t total = R.total;
-        const int nr = R.nruns;
+        const int32_t total = __builtin_amdgcn_readfirstlane(R.total);
+        const int nr = __builtin_amdgcn_readfirstlane(R.nruns);
         const int nbruns = FLUID ? nr / 2 : 0;  // runs [0, nbruns) hold boundary particles
 
         for (int32_t tb = 0; tb < max(total, 1); tb += TILE) {
@@ -370,11 +469,13 @@ __global__ __launch_bounds__(kThreads) void k_interact(PairConsts K, PairArgs A)
             __syncthreads();
 
             // ---- one wavefront per target
-            const int32_t selfbase = FLUID ? R.vstart[R.self_run] - R.s[R.self_run][0] - tb : 0;
+            const int32_t selfbase =
+                FLUID ? __builtin_amdgcn_readfirstlane(R.vstart[R.self_run] - R.s[R.self_run][0]) - tb
+                      : 0;
             for (int32_t a = tbeg + wave; a < tend; a += kWaves) {
                 const int32_t self_v = FLUID ? selfbase + a : -1;  // staging index of a
                 const bool self_here = FLUID && self_v >= 0 && self_v < tlen;
-                const int32_t self_l = self_here ? (int32_t)sMap[self_v] : -1;
+                const int32_t self_l = self_here ? (int32_t)sMap[self_v] : 0;
                 float4 pa, va, aa = make_float4(0.f, 0.f, 0.f, 0.f);
                 if (self_here) {
                     pa = sP[self_l];
@@ -389,6 +490,9 @@ __global__ __launch_bounds__(kThreads) void k_interact(PairConsts K, PairArgs A)
                 // (c0 / rho0) (ta^3 + tb^3) / (ta + tb) = (c0 / rho0) (ta^2 - ta tb + tb^2)
                 const float ta = __builtin_fmaf(va.w, K.inv_rho0, 1.0f);
                 const float ta2 = ta * ta;
+                // forward: Pi_ab = kh (ta^2 - ta tb + tb^2) min(u, 0), u = v.r / (r^2 + eta2),
+                // evaluated as tb (kh tb - kh ta) + kh ta^2
+                const float kta = -K.kh * ta, kta2 = K.kh * ta2;
                 // backward: d(P/rho^2)/drho = c^2 / rho^2 - 2 (P/rho^2) / rho, c = c0 ta^3
                 float dpa = 0.f;
                 if (BWD) {
@@ -396,55 +500,58 @@ __global__ __launch_bounds__(kThreads) void k_interact(PairConsts K, PairArgs A)
                     const float ca = K.c0 * ta2 * ta;
                     dpa = (ca * inv_ra) * (ca * inv_ra) - 2.f * pa.w * inv_ra;
                 }
-                // accumulators: forward (s0..s3 = sum for a.xyz and drho, vmb = max |mu|);
-                // backward (s0..s2 = xbar, s4..s6 = vbar, s3 = rhobar, s7 = alphabar)
+                // accumulators: forward (s0..s3 = sums for a.xyz and drho in units of
+                // gs, vmf = max |u|); backward (s0..s2 = xbar, s3 = rhobar, s4..s6 = vbar,
+                // s7 = alphabar)
                 float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f, s4 = 0.f, s5 = 0.f, s6 = 0.f,
-                      s7 = 0.f;
-                unsigned vmb = 0u;  // bits of max |mu| (non-negative floats order as integers)
+                      s7 = 0.f, vmf = 0.f;
                 unsigned hs = 0;
-                int wp = 0, rp = 0;
+                int wp = 0, rp = 0;          // ring write / read counters (wave-uniform)
+                uint32_t raddr = rfirst;     // this lane's ring entry of the next batch
 
-                auto pair = [&](int idx) {
-                    const float4 pb = sP[idx];
-                    const float4 vb = sV[idx];
+                // one batch: every lane evaluates the pair with the staged entry at
+                // byte offset off
+                auto pair = [&](uint32_t off) {
+                    const float4 pb = lds_load4(sPb + off);
+                    const float4 vb = lds_load4(sVb + off);
                     const float rx = pa.x - pb.x, ry = pa.y - pb.y, rz = pa.z - pb.z;
                     const float r2 = __builtin_fmaf(rz, rz, __builtin_fmaf(ry, ry, rx * rx));
                     const float r = __builtin_amdgcn_sqrtf(r2);
-                    // kernel gradient factor F (grad_a W = F r_ab)
-                    float F, wq = 0.f, qq = 0.f;
+                    // kernel gradient factor in units of gs: F = gs G (grad_a W = F r_ab)
+                    float G, wq = 0.f, qq = 0.f;
                     if (KER == SPH_WENDLAND5) {
                         wq = __builtin_fmaf(-0.5f * K.inv_h, r, 1.0f);
-                        F = K.kf * (wq * wq * wq);
+                        G = wq * wq * wq;
                     } else {
                         qq = r * K.inv_h;
                         const float t = 2.f - qq;
-                        F = qq < 1.f ? K.kc_in * __builtin_fmaf(2.25f, qq, -3.f)
-                                     : K.kc_out * (t * t) * __builtin_amdgcn_rcpf(r);
+                        G = qq < 1.f ? __builtin_fmaf(2.25f, qq, -3.f)
+                                     : K.kco * (t * t) * __builtin_amdgcn_rcpf(r);
                     }
                     const float vx = va.x - vb.x, vy = va.y - vb.y, vz = va.z - vb.z;
                     const float vdr = __builtin_fmaf(vz, rz, __builtin_fmaf(vy, ry, vx * rx));
                     if (!BWD) {
-                        s3 = __builtin_fmaf(vdr, F, s3);
+                        s3 = __builtin_fmaf(vdr, G, s3);
                         if (FLUID) {
-                            const float mu = K.h * vdr * __builtin_amdgcn_rcpf(r2 + K.eta2);
-                            vmb = max(vmb, __builtin_bit_cast(unsigned, fabsf(mu)));
+                            const float u = vdr * __builtin_amdgcn_rcpf(r2 + K.eta2);
+                            vmf = fmaxf(vmf, fabsf(u));
                             const float tb = __builtin_fmaf(vb.w, K.inv_rho0, 1.0f);
-                            const float cr = __builtin_fmaf(tb, tb - ta, ta2);
-                            // Monaghan term, active only for approaching pairs (mu < 0):
-                            // -alpha cbar mu / rhobar = -alpha (c0/rho0) cr min(mu, 0)
-                            const float pi = K.kpi * cr * fminf(mu, 0.f);
-                            const float coef = (pa.w + pb.w + pi) * F;
+                            const float crk = __builtin_fmaf(tb, __builtin_fmaf(tb, K.kh, kta), kta2);
+                            // P_a/rho_a^2 + P_b/rho_b^2 + Pi_ab
+                            const float sm = __builtin_fmaf(crk, fminf(u, 0.f), pa.w + pb.w);
+                            const float coef = sm * G;
                             s0 = __builtin_fmaf(coef, rx, s0);
                             s1 = __builtin_fmaf(coef, ry, s1);
                             s2 = __builtin_fmaf(coef, rz, s2);
                         }
-                        if (STATS) hs += (uint32_t)A.ids[sSlot[idx]] * 2654435761u;
+                        if (STATS) hs += (uint32_t)A.ids[sSlot[off >> 4]] * 2654435761u;
                     } else {
+                        const float F = K.gs * G;
                         // Pair contribution to the loss, symmetric in (a, b):
                         //   (abar_a - abar_b) . T_ab + (Dbar_a + Dbar_b) S_ab,
                         //   T_ab = -m s F r_ab, s = P_a/rho_a^2 + P_b/rho_b^2 + Pi_ab,
                         //   S_ab = m (v_ab . r_ab) F;  its derivatives w.r.t. the gatherer a.
-                        const float4 ab = sA[idx];
+                        const float4 ab = lds_load4(sAb + off);
                         const float dax = aa.x - ab.x, day = aa.y - ab.y, daz = aa.z - ab.z;
                         const float Q = __builtin_fmaf(daz, rz, __builtin_fmaf(day, ry, dax * rx));
                         const float tb = __builtin_fmaf(vb.w, K.inv_rho0, 1.0f);
@@ -491,23 +598,26 @@ __global__ __launch_bounds__(kThreads) void k_interact(PairConsts K, PairArgs A)
                     }
                 };
 
-                // test one chunk of 64 staged candidates; survivors go to the ring,
-                // full batches of 64 are evaluated at once
+                // test one chunk of 64 staged candidates; survivors go to the ring as
+                // byte offsets of their staged entries, full batches of 64 are
+                // evaluated at once.  The ring holds kRing entries in 256 bytes, so
+                // slot k sits at rbase | (2 k mod 256).
                 auto chunk = [&](const float4 pb, int32_t cb0) {
                     const float rx = pa.x - pb.x, ry = pa.y - pb.y, rz = pa.z - pb.z;
                     const float r2 = __builtin_fmaf(rz, rz, __builtin_fmaf(ry, ry, rx * rx));
                     const bool pass = r2 < K.rc2;
                     const unsigned long long m = ballot(pass);
-                    // rank in every lane (no exec-mask switch), then the trash slot
-                    // for the lanes that failed
+                    // rank in every lane (no exec-mask switch); rejected lanes write
+                    // their own trash slot
                     int rk = (int)lane_rank(m);
                     asm volatile("" : "+v"(rk));
-                    const int slot = pass ? ((wp + rk) & (kRing - 1)) : trash;
-                    sRing[wave][slot] = (uint16_t)(cb0 + lane);
+                    const uint32_t w = ((uint32_t)(2 * (wp + rk)) & 0xFEu) | rbase;
+                    *(lds_u16 *)(uintptr_t)(pass ? w : taddr) = (uint16_t)(lane16 + ((uint32_t)cb0 << 4));
                     wp += __popcll(m);
                     if (wp - rp >= kWave) {
                         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-                        pair(sRing[wave][(rp + lane) & (kRing - 1)]);
+                        pair(*(const lds_u16 *)(uintptr_t)raddr);
+                        raddr ^= 2u * kWave;
                         rp += kWave;
                     }
                 };
@@ -528,77 +638,78 @@ __global__ __launch_bounds__(kThreads) void k_interact(PairConsts K, PairArgs A)
                 }
                 if (wp > rp) {
                     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-                    if (lane < wp - rp) pair(sRing[wave][(rp + lane) & (kRing - 1)]);
+                    if (lane < wp - rp) pair(*(const lds_u16 *)(uintptr_t)raddr);
                 }
                 const int cnt = wp - (self_here ? 1 : 0);
                 pairs_acc += (unsigned long long)cnt;
 
                 // ---- reduce over the wave, write (first tile) or accumulate
-                if (!BWD) {
-                    const float tsd = wave_sum(s3);
-                    float tsx = 0.f, tsy = 0.f, tsz = 0.f, tvm = 0.f;
-                    if (FLUID) {
-                        tsx = wave_sum(s0);
-                        tsy = wave_sum(s1);
-                        tsz = wave_sum(s2);
-                        tvm = __builtin_bit_cast(float, wave_max_u(vmb));
-                    }
+                if (!BWD && FLUID) {
+                    // lane l < 4 ends with component l: a.x, a.y, a.z (in units of
+                    // -m gs), drho/dt (in units of m gs)
+                    const float t = wave_sum4(s0, s1, s2, s3, lane, xa);
+                    const float tvm = wave_max_nonneg(vmf, xa) * K.h;
                     unsigned ths = 0;
                     if (STATS) {
                         ths = wave_sum_u(hs);
                         if (self_here) ths -= (uint32_t)A.ids[a] * 2654435761u;
                     }
-                    if (lane == 0) {
-                        float4 o;
-                        if (FLUID)
-                            o = make_float4(-K.mass * tsx, -K.mass * tsy, -K.mass * tsz,
-                                            K.mass * tsd);
-                        else
-                            o = make_float4(0.f, 0.f, 0.f, K.mass * tsd);
+                    if (lane < 4) {
+                        float *o = (float *)A.ace + 4 * (int64_t)a + lane;
+                        float v = (lane < 3 ? -K.mgs : K.mgs) * t;
                         if (tb == 0) {
-                            if (FLUID) { o.x += K.gx; o.y += K.gy; o.z += K.gz; }
-                            A.ace[a] = o;
-                            A.visc[a] = tvm;
+                            v += lane == 0 ? K.gx : lane == 1 ? K.gy : lane == 2 ? K.gz : 0.f;
+                            *o = v;
+                        } else {
+                            *o += v;
+                        }
+                    }
+                    if (lane == 0) {
+                        A.visc[a] = tb == 0 ? tvm : fmaxf(A.visc[a], tvm);
+                        if (STATS) {
+                            if (tb == 0) {
+                                A.stats[2 * a] = cnt;
+                                A.stats[2 * a + 1] = (int32_t)ths;
+                            } else {
+                                A.stats[2 * a] += cnt;
+                                A.stats[2 * a + 1] = (int32_t)((uint32_t)A.stats[2 * a + 1] + ths);
+                            }
+                        }
+                    }
+                } else if (!BWD) {
+                    const float tsd = wave_sum(s3);
+                    unsigned ths = 0;
+                    if (STATS) ths = wave_sum_u(hs);
+                    if (lane == 0) {
+                        const float d = K.mgs * tsd;
+                        if (tb == 0) {
+                            A.ace[a] = make_float4(0.f, 0.f, 0.f, d);
+                            A.visc[a] = 0.f;
                             if (STATS) { A.stats[2 * a] = cnt; A.stats[2 * a + 1] = (int32_t)ths; }
                         } else {
-                            float4 p0s = A.ace[a];
-                            p0s.x += o.x; p0s.y += o.y; p0s.z += o.z; p0s.w += o.w;
-                            A.ace[a] = p0s;
-                            A.visc[a] = fmaxf(A.visc[a], tvm);
+                            A.ace[a].w += d;
                             if (STATS) {
                                 A.stats[2 * a] += cnt;
                                 A.stats[2 * a + 1] = (int32_t)((uint32_t)A.stats[2 * a + 1] + ths);
                             }
                         }
                     }
+                } else if (FLUID) {
+                    // lane l < 8 ends with s_l: xbar.xyz, rhobar, vbar.xyz, alphabar
+                    const float t = wave_sum8(s0, s1, s2, s3, s4, s5, s6, s7, lane, xa);
+                    if (lane < 8) {
+                        const float v = K.mass * t;
+                        if (lane < 3) {
+                            ((float *)A.xbar)[4 * (int64_t)a + lane] += v;
+                        } else if (lane < 7) {
+                            ((float *)A.vbar)[4 * (int64_t)a + (lane == 3 ? 3 : lane - 4)] += v;
+                        } else {
+                            A.alpha_part[a] = (tb == 0 ? 0.f : A.alpha_part[a]) + v;
+                        }
+                    }
                 } else {
                     const float tr = wave_sum(s3);
-                    float t0 = 0.f, t1 = 0.f, t2 = 0.f, t4 = 0.f, t5 = 0.f, t6 = 0.f, t7 = 0.f;
-                    if (FLUID) {
-                        t0 = wave_sum(s0);
-                        t1 = wave_sum(s1);
-                        t2 = wave_sum(s2);
-                        t4 = wave_sum(s4);
-                        t5 = wave_sum(s5);
-                        t6 = wave_sum(s6);
-                        t7 = wave_sum(s7);
-                    }
-                    if (lane == 0) {
-                        float4 vbo = A.vbar[a];
-                        vbo.w += K.mass * tr;
-                        if (FLUID) {
-                            float4 xbo = A.xbar[a];
-                            xbo.x += K.mass * t0;
-                            xbo.y += K.mass * t1;
-                            xbo.z += K.mass * t2;
-                            A.xbar[a] = xbo;
-                            vbo.x += K.mass * t4;
-                            vbo.y += K.mass * t5;
-                            vbo.z += K.mass * t6;
-                            A.alpha_part[a] = (tb == 0 ? 0.f : A.alpha_part[a]) + K.mass * t7;
-                        }
-                        A.vbar[a] = vbo;
-                    }
+                    if (lane == 0) A.vbar[a].w += K.mass * tr;
                 }
             }
             __syncthreads();
@@ -681,6 +792,15 @@ static PairConsts pair_consts(const sph_grid *g, const sph_params *p, int32_t n)
     K.kcr_in = (float)(2.25 * ac / (h * h * h));
     K.kcr_out = (float)(0.75 * ac / h);
     K.kernel = p->kernel;
+    K.kh = (float)(-p->alpha * p->c0 / p->rho0 * h);
+    if (p->kernel == SPH_CUBIC_SPLINE) {
+        K.gs = K.kc_in;
+        K.kco = (float)(-0.75 * h);  // kc_out / kc_in
+    } else {
+        K.gs = K.kf;
+        K.kco = 0.f;
+    }
+    K.mgs = (float)(p->mass * (double)K.gs);
     K.c0 = (float)p->c0;
     K.rho0 = (float)p->rho0;
     K.inv_rho0 = (float)(1.0 / p->rho0);

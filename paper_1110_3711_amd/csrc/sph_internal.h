@@ -106,6 +106,12 @@ struct PairConsts {
     float kcr_in;    // 9 aD / (4 h^3)
     float kcr_out;   // 3 aD / (4h)
     int32_t kernel;  // SPH_WENDLAND5 or SPH_CUBIC_SPLINE (selects the instantiation)
+    // forward pair sums carry G = F / gs (Wendland: G = (1 - q/2)^3, gs = kf;
+    // cubic: G = 9q/4 - 3 or kco (2 - q)^2 / r, gs = kc_in)
+    float gs;
+    float kco;       // cubic: kc_out / kc_in = -3h/4
+    float mgs;       // mass * gs
+    float kh;        // -alpha h c0 / rho0: Pi_ab = kh cr min(u, 0), mu = h u
     float c0;
     float rho0;
     float inv_rho0;
