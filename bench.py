@@ -8,8 +8,9 @@ rebuilt every step.  One step = sph_build_cells -> sph_interact -> sph_step
 
 Prints ONE JSON line.  ``value`` is directed pair interactions per second over
 the K timed steps (inputs resident in HBM, no host transfer inside the timed
-region).  ``roofline`` reports the fluid-target pair kernel (the dominant
-kernel) against the FP32 vector ALU peak; ``cpu_baseline`` times the FP64
+region).  ``roofline`` reports the pair kernel (one fused launch per step:
+fluid targets, then boundary targets; the dominant kernel) against the FP32
+vector ALU peak; ``cpu_baseline`` times the FP64
 oracle on the host cores on a bounded sample of the same workload.
 """
 
@@ -86,11 +87,13 @@ def cpu_baseline(layout, budget_s: float = 12.0):
 
 def adjoint_ratio(layout, steps: int, every: int):
     """Wall time of the checkpointed backward pass (recompute + adjoint) over
-    the forward pass of the same rollout (both on the device, synchronised)."""
+    the forward pass of the same rollout (both on the device, synchronised),
+    and the peak device memory of the pair."""
     import torch
 
     from paper_1110_3711_amd.rollout import Rollout
 
+    torch.cuda.reset_peak_memory_stats()
     roll = Rollout(layout, steps, every)
     v0 = torch.as_tensor(layout.v[layout.nb:], dtype=torch.float64, device=roll.device)
     rng = np.random.default_rng(7)
@@ -111,9 +114,10 @@ def adjoint_ratio(layout, steps: int, every: int):
     torch.cuda.synchronize()
     t2 = time.perf_counter()
     ok = bool(torch.isfinite(gv).all().item()) and bool(torch.isfinite(ga).item())
-    return {"ratio": (t2 - t1) / (t1 - t0), "forward_s": t1 - t0, "backward_s": t2 - t1,
-            "steps": steps, "checkpoint_every": every, "finite": ok,
-            "alpha_grad": float(ga.item())}
+    return {"workload": layout.name, "particles": layout.n, "ratio": (t2 - t1) / (t1 - t0),
+            "forward_s": t1 - t0, "backward_s": t2 - t1, "steps": steps,
+            "checkpoint_every": every, "finite": ok, "alpha_grad": float(ga.item()),
+            "peak_device_bytes": int(torch.cuda.max_memory_allocated())}
 
 
 def main():
@@ -125,8 +129,10 @@ def main():
     ap.add_argument("--nsub", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=12.0)
-    ap.add_argument("--adjoint-steps", type=int, default=50)
-    ap.add_argument("--adjoint-every", type=int, default=10)
+    ap.add_argument("--adjoint-config", default="cfg4",
+                    help="layout of the differentiable rollout (default: the 64k-fluid case)")
+    ap.add_argument("--adjoint-steps", type=int, default=200)
+    ap.add_argument("--adjoint-every", type=int, default=20)
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one 256 MiB device-to-device copy first (counter calibration)")
@@ -149,6 +155,7 @@ def main():
         torch.cuda.synchronize()
         del a, b
     lay = named_case(args.config)
+    torch.cuda.reset_peak_memory_stats()
     sim = sph.Simulation(lay, nsub=args.nsub)
     stream = torch.cuda.current_stream()
 
@@ -160,8 +167,7 @@ def main():
         raise SystemExit("non-finite state during warmup")
 
     K = args.steps
-    npairs_f = torch.zeros(1, dtype=torch.int64, device=sim.device)
-    npairs_b = torch.zeros(1, dtype=torch.int64, device=sim.device)
+    npairs = torch.zeros(2, dtype=torch.int64, device=sim.device)  # fluid, boundary targets
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
           for _ in range(K)]
     start = torch.cuda.Event(enable_timing=True)
@@ -171,9 +177,8 @@ def main():
     t0 = time.perf_counter()
     for k in range(K):
         sim.build_cells()
-        sim.interact(parts=sph.SPH_PI_BOUNDARY, npairs=npairs_b)
         ev[k][0].record(stream)
-        sim.interact(parts=sph.SPH_PI_FLUID, npairs=npairs_f)
+        sim.interact(parts=sph.SPH_PI_ALL, npairs=npairs)
         ev[k][1].record(stream)
         sim.update()
     stop.record(stream)
@@ -183,26 +188,30 @@ def main():
     status = sim.dev_status()
     if status & sph.SPH_DEV_NONFINITE:
         raise SystemExit("non-finite state in the timed region")
-    fluid_ms = np.array([a.elapsed_time(b) for a, b in ev])
-    pf = int(npairs_f.item())
-    pb = int(npairs_b.item())
+    pi_ms = np.array([a.elapsed_time(b) for a, b in ev])
+    pf = int(npairs[0].item())
+    pb = int(npairs[1].item())
     pairs = pf + pb
     t = gpu_ms / 1e3
     ms_step = gpu_ms / K
 
-    flop_launch = pf / K * FLOP_FLUID_PAIR
-    achieved = flop_launch / (fluid_ms.mean() / 1e3)
+    # one fused pair-kernel launch per step: fluid targets (F-F + F-B), then
+    # boundary targets (B-F)
+    flop_launch = (pf * FLOP_FLUID_PAIR + pb * FLOP_BOUND_PAIR) / K
+    achieved = flop_launch / (pi_ms.mean() / 1e3)
     roof = {
         "bound": "alu",
-        "kernel": "k_interact<fluid> (F-F + F-B pair loop)",
+        "kernel": "k_interact<fused> (fluid targets F-F + F-B, then boundary targets B-F)",
         "achieved": achieved / 1e12,
         "peak": PEAK_FP32_VECTOR / 1e12,
         "unit": "TFLOP/s",
         "frac": achieved / PEAK_FP32_VECTOR,
         "traffic": _traffic_record(),
-        "avg_launch_ms": float(fluid_ms.mean()),
-        "pairs_per_launch": pf / K,
-        "flop_per_pair": FLOP_FLUID_PAIR,
+        "avg_launch_ms": float(pi_ms.mean()),
+        "pairs_per_launch": (pf + pb) / K,
+        "fluid_target_pairs_per_launch": pf / K,
+        "boundary_target_pairs_per_launch": pb / K,
+        "flop_per_pair": {"fluid_target": FLOP_FLUID_PAIR, "boundary_target": FLOP_BOUND_PAIR},
     }
 
     out = {
@@ -236,11 +245,15 @@ def main():
         "adjoint_forward_ratio": None,
         "adjoint": None,
         "dev_status": status,
+        "peak_device_bytes": int(torch.cuda.max_memory_allocated()),
         "paper_context": PAPER_CONTEXT,
         "roofline": roof,
     }
     if not args.no_adjoint:
-        adj = adjoint_ratio(lay, args.adjoint_steps, args.adjoint_every)
+        del sim
+        torch.cuda.empty_cache()
+        alay = lay if args.adjoint_config == args.config else named_case(args.adjoint_config)
+        adj = adjoint_ratio(alay, args.adjoint_steps, args.adjoint_every)
         out["adjoint"] = adj
         out["adjoint_forward_ratio"] = adj["ratio"]
     if not args.no_cpu_baseline:

@@ -177,13 +177,16 @@ SPH_API sph_status sph_build_cells(const sph_grid *g, const sph_state *src, sph_
  *   ace[a].xyz = g - m sum_b (P_a/rho_a^2 + P_b/rho_b^2 + Pi_ab) F_ab r_ab
  *   ace[a].w   = m sum_b (v_a - v_b).r_ab F_ab              (drho/dt)
  *   visc[a]    = max_b |mu_ab|
- * with grad_a W_ab = F_ab r_ab (Wendland quintic), mu_ab = h v_ab.r_ab /
+ * with grad_a W_ab = F_ab r_ab (the kernel p->kernel), mu_ab = h v_ab.r_ab /
  * (r^2 + eta2), Pi_ab = -alpha cbar mu_ab / rhobar when v_ab.r_ab < 0 else 0,
  * Tait P = B((rho/rho0)^7 - 1), c = c0 (rho/rho0)^3.  Boundary targets get
  * (0, 0, 0, drho/dt) over fluid neighbours and visc 0; excluded slots get 0.
- * parts: SPH_PI_FLUID and/or SPH_PI_BOUNDARY (each enqueues one pair kernel
- * plus a one-wave counter reset; a full stage is SPH_PI_ALL).
- * npairs (may be NULL): += number of directed interacting pairs (u64).
+ * parts: SPH_PI_FLUID and/or SPH_PI_BOUNDARY.  SPH_PI_ALL (a full stage)
+ * enqueues a counter reset, the boundary-cell filter and ONE pair kernel that
+ * takes the fluid target cells and then the boundary cells with fluid in
+ * reach; a single part enqueues that part's own pair kernel.
+ * npairs (may be NULL): [2] u64, npairs[0] += directed interacting pairs with
+ * a fluid target, npairs[1] += those with a boundary target.
  * nbr_stats (may be NULL, diagnostic, slower): [2n] per slot (neighbour
  * count, sum over neighbours of uint32(id * 2654435761)). */
 #define SPH_PI_FLUID 1u    /* fluid targets: F-F + F-B (Section 4.5 fused kernel) */

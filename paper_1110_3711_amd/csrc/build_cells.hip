@@ -11,27 +11,27 @@
 namespace sph {
 
 // ---------------------------------------------------------------------------
-// keys
+// keys (computed on the fly by the first radix pass)
 
-__global__ void k_keys(int32_t n, int32_t nb, int32_t ncell, const int32_t *__restrict__ cell,
-                       uint32_t *__restrict__ keys, uint32_t *__restrict__ vals)
+struct KeySrc {
+    const uint32_t *keys;   // later passes: keys of the previous pass
+    const int32_t *cell;    // first pass: cell of slot i (keys == nullptr)
+    int32_t nb, ncell;
+};
+
+__device__ inline uint32_t key_of(const KeySrc &S, int64_t i)
 {
-    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const int32_t c = cell[i];
-    uint32_t k;
-    if (c == SPH_EXCLUDED) k = 2u * (uint32_t)ncell;
-    else k = (uint32_t)c + (i < nb ? 0u : (uint32_t)ncell);
-    keys[i] = k;
-    vals[i] = (uint32_t)i;
+    if (S.keys) return S.keys[i];
+    const int32_t c = S.cell[i];
+    if (c == SPH_EXCLUDED) return 2u * (uint32_t)S.ncell;
+    return (uint32_t)c + (i < S.nb ? 0u : (uint32_t)S.ncell);
 }
 
 // ---------------------------------------------------------------------------
 // radix sort: per-block digit histograms, digit-major so that one exclusive
 // scan gives every (digit, block) its global output offset.
 
-__global__ __launch_bounds__(kSortThreads) void k_radix_hist(int32_t n, int shift,
-                                                             const uint32_t *__restrict__ keys,
+__global__ __launch_bounds__(kSortThreads) void k_radix_hist(int32_t n, int shift, KeySrc keys,
                                                              uint32_t *__restrict__ hist,
                                                              int nblk)
 {
@@ -41,7 +41,7 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_hist(int32_t n, int shif
     const int64_t base = (int64_t)blockIdx.x * kSortTile;
     for (int j = 0; j < kSortItems; ++j) {
         const int64_t e = base + (int64_t)j * kSortThreads + threadIdx.x;
-        if (e < n) atomicAdd(&h[(keys[e] >> shift) & (kRadix - 1)], 1u);
+        if (e < n) atomicAdd(&h[(key_of(keys, e) >> shift) & (kRadix - 1)], 1u);
     }
     __syncthreads();
     for (int d = threadIdx.x; d < kRadix; d += kSortThreads)
@@ -54,7 +54,7 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_hist(int32_t n, int shif
 // waves through per-wave digit counts in LDS; across rounds through running
 // digit counters.
 __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
-    int32_t n, int shift, const uint32_t *__restrict__ keys_in, const uint32_t *__restrict__ vals_in,
+    int32_t n, int shift, KeySrc keys_in, const uint32_t *__restrict__ vals_in,
     uint32_t *__restrict__ keys_out, uint32_t *__restrict__ vals_out,
     const uint32_t *__restrict__ offs, int nblk)
 {
@@ -72,8 +72,8 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
         const bool valid = e < n;
         uint32_t key = 0, val = 0, dig = 0;
         if (valid) {
-            key = keys_in[e];
-            val = vals_in[e];
+            key = key_of(keys_in, e);
+            val = vals_in ? vals_in[e] : (uint32_t)e;  // first pass: slot index
             dig = (key >> shift) & (kRadix - 1);
         }
         unsigned long long peers = ballot(valid);
@@ -123,17 +123,25 @@ __device__ T block_exclusive_scan(T v, T *sh, T *total)
     return incl - v;
 }
 
-template <typename T>
+// MARK: the scanned value of element e is a[e] | 1 when a[e] != 0 (the
+// packed (count << 32 | non-empty) key counts), applied on load.
+template <typename T, bool MARK>
+__device__ inline T scan_load(const T *a, int64_t e, int64_t len)
+{
+    if (e >= len) return (T)0;
+    const T v = a[e];
+    return MARK ? (v ? (T)(v | (T)1) : (T)0) : v;
+}
+
+template <typename T, bool MARK>
 __global__ __launch_bounds__(kScanThreads) void k_scan_reduce(int64_t len, const T *__restrict__ a,
                                                               unsigned long long *__restrict__ part)
 {
     __shared__ T sh[kScanThreads];
     const int64_t base = (int64_t)blockIdx.x * kScanTile;
     T s = 0;
-    for (int j = 0; j < kScanItems; ++j) {
-        const int64_t e = base + (int64_t)j * kScanThreads + threadIdx.x;
-        if (e < len) s += a[e];
-    }
+    for (int j = 0; j < kScanItems; ++j)
+        s += scan_load<T, MARK>(a, base + (int64_t)j * kScanThreads + threadIdx.x, len);
     T tot;
     block_exclusive_scan<T>(s, sh, &tot);
     if (threadIdx.x == 0) part[blockIdx.x] = (unsigned long long)tot;
@@ -167,23 +175,39 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_partials(int64_t np,
     }
 }
 
-template <typename T>
+// PREFIX: part[] holds tile totals and each block sums those before its own
+// tile (few tiles); otherwise part[] already holds the exclusive prefixes.
+template <typename T, bool MARK, bool PREFIX>
 __global__ __launch_bounds__(kScanThreads) void k_scan_apply(int64_t len, T *__restrict__ a,
                                                              const unsigned long long *__restrict__ part)
 {
     // blocked: thread t owns kScanItems consecutive elements
     __shared__ T sh[kScanThreads];
+    __shared__ unsigned long long sp[kScanThreads];
+    unsigned long long base;
+    if (PREFIX) {
+        unsigned long long pre = 0;
+        for (int64_t i = threadIdx.x; i < (int64_t)blockIdx.x; i += kScanThreads) pre += part[i];
+        sp[threadIdx.x] = pre;
+        __syncthreads();
+        for (int o = kScanThreads / 2; o > 0; o >>= 1) {
+            if ((int)threadIdx.x < o) sp[threadIdx.x] += sp[threadIdx.x + o];
+            __syncthreads();
+        }
+        base = sp[0];
+    } else {
+        base = part[blockIdx.x];
+    }
     const int64_t first = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
     T loc[kScanItems];
     T s = 0;
     for (int j = 0; j < kScanItems; ++j) {
-        const int64_t e = first + j;
-        loc[j] = e < len ? a[e] : (T)0;
+        loc[j] = scan_load<T, MARK>(a, first + j, len);
         s += loc[j];
     }
     T tot;
     const T ex = block_exclusive_scan<T>(s, sh, &tot);
-    T run = (T)part[blockIdx.x] + ex;
+    T run = (T)base + ex;
     for (int j = 0; j < kScanItems; ++j) {
         const int64_t e = first + j;
         if (e < len) a[e] = run;
@@ -193,15 +217,22 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_apply(int64_t len, T *__r
 
 // The reduce step above sums a strided layout and the apply step a blocked
 // one; both cover exactly the tile [b * kScanTile, (b + 1) * kScanTile), so
-// the per-tile totals agree.
-template <typename T>
+// the per-tile totals agree.  Up to kScanFusedTiles tiles the apply blocks add
+// up the tile totals themselves (two launches); beyond, one block scans them.
+constexpr int64_t kScanFusedTiles = 1024;
+
+template <typename T, bool MARK = false>
 static hipError_t exclusive_scan(T *a, int64_t len, unsigned long long *part, hipStream_t s)
 {
     if (len <= 0) return hipSuccess;
     const int64_t nblk = (len + kScanTile - 1) / kScanTile;
-    k_scan_reduce<T><<<(unsigned)nblk, kScanThreads, 0, s>>>(len, a, part);
-    k_scan_partials<<<1, kScanThreads, 0, s>>>(nblk, part);
-    k_scan_apply<T><<<(unsigned)nblk, kScanThreads, 0, s>>>(len, a, part);
+    k_scan_reduce<T, MARK><<<(unsigned)nblk, kScanThreads, 0, s>>>(len, a, part);
+    if (nblk <= kScanFusedTiles) {
+        k_scan_apply<T, MARK, true><<<(unsigned)nblk, kScanThreads, 0, s>>>(len, a, part);
+    } else {
+        k_scan_partials<<<1, kScanThreads, 0, s>>>(nblk, part);
+        k_scan_apply<T, MARK, false><<<(unsigned)nblk, kScanThreads, 0, s>>>(len, a, part);
+    }
     return hipGetLastError();
 }
 
@@ -236,17 +267,8 @@ __global__ void k_count_keys(int32_t n, const uint32_t *__restrict__ keys,
     }
 }
 
-__global__ void k_mark_nonempty(int64_t nkeys, unsigned long long *__restrict__ ks)
-{
-    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k < nkeys) {
-        const unsigned long long v = ks[k];
-        if (v) ks[k] = v | 1ull;
-    }
-}
-
-// After the exclusive scan, ks[k] = (first slot of key k) << 32 | (number of
-// non-empty keys before k).
+// After the exclusive scan (with the non-empty mark), ks[k] = (first slot of
+// key k) << 32 | (number of non-empty keys before k).
 __global__ void k_emit_ranges(int64_t nkeys, int32_t n, int32_t ncell,
                               const unsigned long long *__restrict__ ks,
                               int32_t *__restrict__ start, int32_t *__restrict__ list,
@@ -307,31 +329,34 @@ hipError_t launch_build_cells(const sph_grid *g, const sph_state *src, sph_state
     dst->n = src->n;
     dst->nb = src->nb;
 
-    // 1. keys
-    if (n > 0)
-        k_keys<<<(n + threads - 1) / threads, threads, 0, s>>>(n, src->nb, ncell, src->cell,
-                                                                  w.keys0, w.vals0);
-    // 2. radix sort over the bits of the largest key
+    // 1-2. radix sort over the bits of the largest key; the first pass reads
+    // the keys from the cell array and the values are the slots
     int bits = 0;
     while (bits < 32 && ((uint64_t)1 << bits) <= (uint64_t)(2 * (int64_t)ncell)) ++bits;
-    uint32_t *kin = w.keys0, *vin = w.vals0, *kout = w.keys1, *vout = w.vals1;
+    uint32_t *kin = nullptr, *vin = nullptr, *kout = w.keys0, *vout = w.vals0;
     const int nblk = nblk_sort(n);
     for (int shift = 0; shift < bits && n > 0; shift += kRadixBits) {
-        k_radix_hist<<<nblk, kSortThreads, 0, s>>>(n, shift, kin, w.hist, nblk);
+        const KeySrc ks{kin, src->cell, src->nb, ncell};
+        k_radix_hist<<<nblk, kSortThreads, 0, s>>>(n, shift, ks, w.hist, nblk);
         hipError_t e = exclusive_scan<uint32_t>(w.hist, (int64_t)kRadix * nblk, w.partials, s);
         if (e != hipSuccess) return e;
-        k_radix_scatter<<<nblk, kSortThreads, 0, s>>>(n, shift, kin, vin, kout, vout, w.hist, nblk);
-        uint32_t *t;
-        t = kin; kin = kout; kout = t;
-        t = vin; vin = vout; vout = t;
+        k_radix_scatter<<<nblk, kSortThreads, 0, s>>>(n, shift, ks, vin, kout, vout, w.hist, nblk);
+        if (kin == nullptr) {
+            kin = kout;
+            vin = vout;
+            kout = w.keys1;
+            vout = w.vals1;
+        } else {
+            uint32_t *t;
+            t = kin; kin = kout; kout = t;
+            t = vin; vin = vout; vout = t;
+        }
     }
     // 3. key counts -> packed (count, non-empty) -> exclusive scan -> ranges
     const int64_t lenks = nkeys + 1;
     k_fill_u64<<<(unsigned)((lenks + threads - 1) / threads), threads, 0, s>>>(lenks, w.keyscan);
     if (n > 0) k_count_keys<<<(n + threads - 1) / threads, threads, 0, s>>>(n, kin, w.keyscan);
-    k_mark_nonempty<<<(unsigned)((nkeys + threads - 1) / threads), threads, 0, s>>>(nkeys,
-                                                                                   w.keyscan);
-    hipError_t e = exclusive_scan<unsigned long long>(w.keyscan, lenks, w.partials, s);
+    hipError_t e = exclusive_scan<unsigned long long, true>(w.keyscan, lenks, w.partials, s);
     if (e != hipSuccess) return e;
     k_emit_ranges<<<(unsigned)((lenks + threads - 1) / threads), threads, 0, s>>>(
         nkeys, n, ncell, w.keyscan, cells->start, cells->list, cells->info);

@@ -253,10 +253,11 @@ __device__ void build_runs(const PairConsts &K, const int32_t *__restrict__ star
 // pair kernel: forward (targets) and backward (gatherers) share the work
 // queue, the stencil staging and the ballot compaction.
 
-enum Kind { kFwdFluid = 0, kFwdBound = 1, kBwdFluid = 2, kBwdBound = 3 };
+enum Kind { kFwdFluid = 0, kFwdBound = 1, kBwdFluid = 2, kBwdBound = 3, kFwdAll = 4, kBwdAll = 5 };
 
 struct PairArgs {
     const int32_t *start, *items, *counts;
+    const int32_t *items2, *counts2;  // fused launches: active boundary cells, their count
     const float4 *pos, *velrho;
     const int32_t *ids;
     float4 *ace;        // forward: out (a, drho/dt); backward: in (abar, Dbar)
@@ -264,64 +265,474 @@ struct PairArgs {
     float4 *xbar;       // backward: pos_bar (+=)
     float4 *vbar;       // backward: velrho_bar (+=)
     float *alpha_part;  // backward: per-slot alpha adjoint of fluid targets
-    int32_t *queue;
-    unsigned long long *npairs;
+    int32_t *queue;     // kXcds counters of the first work list
+    int32_t *queue2;    // fused launches: counter of the boundary work list
+    unsigned long long *npairs;  // [2]: += fluid-target, boundary-target pairs
     int32_t *stats;
 };
 
+// A launch runs one work list (fluid target cells or active boundary cells),
+// or both in turn (the fused kinds: fluid cells first, then boundary cells,
+// so the short boundary items fill the tail of the launch).
 template <int KIND>
 struct KindTraits {
-    static constexpr bool fluid = KIND == kFwdFluid || KIND == kBwdFluid;
-    static constexpr bool bwd = KIND >= kBwdFluid;
+    static constexpr bool fused = KIND == kFwdAll || KIND == kBwdAll;
+    static constexpr bool bwd = KIND == kBwdFluid || KIND == kBwdBound || KIND == kBwdAll;
+    static constexpr bool fluid = KIND == kFwdFluid || KIND == kBwdFluid || fused;  // first list
     static constexpr int tile = bwd ? 1280 : kTile;  // LDS: 32 B (forward) / 48 B per candidate
+    static constexpr int first = fused ? (bwd ? kBwdFluid : kFwdFluid) : KIND;
+    static constexpr int second = bwd ? kBwdBound : kFwdBound;
 };
 
-template <int KIND, bool STATS, int KER>
-__global__ __launch_bounds__(kThreads) void k_interact(PairConsts K, PairArgs A)
+// LDS of one workgroup
+template <int TILE, bool BWD, bool STATS>
+struct PairLds {
+    static constexpr int STAGE = (TILE + kThreads - 1) / kThreads;
+    float4 sP[TILE + 2 * kWave];            // (offset in target frame, P/rho^2) + padding
+    float4 sV[TILE];                        // (v, rho - rho0)
+    float4 sA[BWD ? TILE : 1];              // backward: (abar, Dbar), abar = 0 on boundary
+    alignas(256) uint16_t sRing[kWaves][kRing];  // 256 bytes per wave
+    uint16_t sTrash[kWaves][kWave];         // rejected candidates land here
+    uint16_t sMap[TILE];                    // staging index -> sorted slot
+    uint16_t sCnt[STAGE][kWaves][kBins];
+    int32_t sBin[kBins + 1];                // first sorted slot of each x-bin
+    int32_t sSlot[STATS ? TILE : 1];        // candidate slot (diagnostics only)
+    RunTable R;
+    int32_t sItem;
+};
+
+// per-lane constants: LDS byte addresses of this wave's ring (256-aligned),
+// the lane's first read entry and trash slot, the staged arrays
+struct LaneCtx {
+    int lane, wave;
+    uint32_t rbase, rfirst, lane16, taddr, sPb, sVb, sAb;
+    XorAddr xa;
+};
+
+// One work item: the targets of cell `key` (of the list kind KIND) against
+// its stencil, staged tile by tile through the workgroup's LDS.
+template <int KIND, bool STATS, int KER, class L>
+__device__ __forceinline__ void pair_item(const PairConsts &K, const PairArgs &A, L &S,
+                                          const LaneCtx &C, int32_t key,
+                                          unsigned long long &pairs_acc)
 {
     using T = KindTraits<KIND>;
     constexpr bool FLUID = T::fluid;
     constexpr bool BWD = T::bwd;
     constexpr int TILE = T::tile;
-    constexpr int STAGE = (TILE + kThreads - 1) / kThreads;
-    __shared__ float4 sP[TILE + 2 * kWave];       // (offset in target frame, P/rho^2) + padding
-    __shared__ float4 sV[TILE];                   // (v, rho - rho0)
-    __shared__ float4 sA[BWD ? TILE : 1];         // backward: (abar, Dbar), abar = 0 on boundary
-    __shared__ __align__(256) uint16_t sRing[kWaves][kRing];  // 256 bytes per wave
-    __shared__ uint16_t sTrash[kWaves][kWave];                // rejected candidates land here
-    __shared__ uint16_t sMap[TILE];               // staging index -> sorted slot
-    __shared__ uint16_t sCnt[STAGE][kWaves][kBins];
-    __shared__ int32_t sBin[kBins + 1];           // first sorted slot of each x-bin
-    __shared__ int32_t sSlot[STATS ? TILE : 1];   // candidate slot (diagnostics only)
-    __shared__ RunTable R;
-    __shared__ int32_t sItem;
-
+    constexpr int STAGE = L::STAGE;
+    auto &sP = S.sP;
+    auto &sV = S.sV;
+    auto &sA = S.sA;
+    auto &sMap = S.sMap;
+    auto &sCnt = S.sCnt;
+    auto &sBin = S.sBin;
+    auto &sSlot = S.sSlot;
+    auto &R = S.R;
+    const int lane = C.lane, wave = C.wave;
+    const uint32_t rbase = C.rbase, rfirst = C.rfirst, lane16 = C.lane16, taddr = C.taddr;
+    const uint32_t sPb = C.sPb, sVb = C.sVb, sAb = C.sAb;
+    const XorAddr xa = C.xa;
     auto xbin = [&](float x) { return min(max((int)((x - K.xlo) * K.xscale), 0), kBins - 1); };
 
-    const int lane = threadIdx.x & (kWave - 1);
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
-    // LDS byte addresses: ring of this wave (256-aligned), its first read entry
-    // per lane, this lane's trash slot, and the staged arrays
-    uint32_t rbase = lds_addr(&sRing[wave][0]);
-    const uint32_t rfirst = rbase | (2u * lane);
+    const int32_t c = FLUID ? max(key - K.ncell, 0) : min(key, K.ncell - 1);
+    const int32_t cx = c % K.nc0, cy = (c / K.nc0) % K.nc1, cz = c / (K.nc0 * K.nc1);
+    const int32_t tbeg = __builtin_amdgcn_readfirstlane(min(max(A.start[key], 0), K.n));
+    const int32_t tend = __builtin_amdgcn_readfirstlane(min(max(A.start[key + 1], tbeg), K.n));
+
+    build_runs<FLUID>(K, A.start, cx, cy, cz, R);
+    const int32_t total = __builtin_amdgcn_readfirstlane(R.total);
+    const int nr = __builtin_amdgcn_readfirstlane(R.nruns);
+    const int nbruns = FLUID ? nr / 2 : 0;  // runs [0, nbruns) hold boundary particles
+
+    for (int32_t tb = 0; tb < max(total, 1); tb += TILE) {
+        const int32_t tlen = max(min(TILE, total - tb), 0);
+        // ---- stage candidates [tb, tb + tlen) into LDS, ordered by the x-bin of
+        //      their position in the target frame (stable in staging order), so
+        //      that each target scans one contiguous window |x_a - x_b| < 2h
+        // locate staging index l: slot j of the sorted state and its run
+        auto locate = [&](int32_t l, int32_t &j, int &run) {
+            const int32_t v = tb + min(l, max(tlen - 1, 0));
+            int lo = 0, hi = nr;  // find r with vstart[r] <= v < vstart[r+1]
+            while (hi - lo > 1) {
+                const int mid = (lo + hi) >> 1;
+                if (R.vstart[mid] <= v) lo = mid;
+                else hi = mid;
+            }
+            j = min(max(R.s[lo][0] + (v - R.vstart[lo]), 0), K.n - 1);
+            run = lo;
+        };
+        // frame shift (k_b - k_a) cell along x, exact
+        auto shift_x = [&](int32_t j, int run) {
+            int ci = 0;
+            for (int i = 1; i < R.ncx[run]; ++i) ci += R.s[run][i] <= j ? 1 : 0;
+            return (float)(R.dx0[run] + ci) * K.cellf;
+        };
+        // rank among the equal x-bins of this wave (stable in lane order)
+        auto rank_round = [&](int u, int bin) {
+            const bool valid = (int32_t)(threadIdx.x + u * kThreads) < tlen;
+            unsigned long long peers = ballot(valid);
+            for (int b = 0; b < kBinBits; ++b) {
+                const bool bit = (bin >> b) & 1;
+                const unsigned long long mb = ballot(bit);
+                peers &= bit ? mb : ~mb;
+            }
+            const int rk = (int)lane_rank(peers);
+            if (valid && rk == 0) sCnt[u][wave][bin] = (uint16_t)__popcll(peers);
+            return rk;
+        };
+        static_assert(STAGE <= 4, "staging rounds");
+        for (int i = threadIdx.x; i < STAGE * kWaves * kBins; i += kThreads)
+            (&sCnt[0][0][0])[i] = 0;
+        // pass A: locate all of this thread's candidates, then one round of loads
+        int32_t j0 = 0, j1 = 0, j2 = 0, j3 = 0;
+        int q0 = 0, q1 = 0, q2 = 0, q3 = 0;
+        locate(threadIdx.x, j0, q0);
+        if (STAGE > 1) locate(threadIdx.x + kThreads, j1, q1);
+        if (STAGE > 2) locate(threadIdx.x + 2 * kThreads, j2, q2);
+        if (STAGE > 3) locate(threadIdx.x + 3 * kThreads, j3, q3);
+        const float x0 = A.pos[j0].x, x1 = STAGE > 1 ? A.pos[j1].x : 0.f,
+                    x2 = STAGE > 2 ? A.pos[j2].x : 0.f, x3 = STAGE > 3 ? A.pos[j3].x : 0.f;
+        const int bn0 = xbin(x0 + shift_x(j0, q0));
+        const int bn1 = STAGE > 1 ? xbin(x1 + shift_x(j1, q1)) : 0;
+        const int bn2 = STAGE > 2 ? xbin(x2 + shift_x(j2, q2)) : 0;
+        const int bn3 = STAGE > 3 ? xbin(x3 + shift_x(j3, q3)) : 0;
+        __syncthreads();
+        const int rk0 = rank_round(0, bn0);
+        const int rk1 = STAGE > 1 ? rank_round(1, bn1) : 0;
+        const int rk2 = STAGE > 2 ? rank_round(2, bn2) : 0;
+        const int rk3 = STAGE > 3 ? rank_round(3, bn3) : 0;
+        __syncthreads();
+        if ((int)threadIdx.x < kBins) {  // per-bin offsets over (round, wave)
+            const int b = threadIdx.x;
+            int run = 0;
+            for (int u = 0; u < STAGE; ++u)
+                for (int w = 0; w < kWaves; ++w) {
+                    const int cc = sCnt[u][w][b];
+                    sCnt[u][w][b] = (uint16_t)run;
+                    run += cc;
+                }
+            sBin[b + 1] = run;
+        }
+        __syncthreads();
+        if (threadIdx.x < kWave) {  // bin starts: exclusive scan of the bin totals
+            const int ln = threadIdx.x;
+            int32_t v = ln < kBins ? sBin[ln + 1] : 0;
+            for (int o = 1; o < kWave; o <<= 1) {
+                const int32_t t = __shfl_up(v, o);
+                if (ln >= o) v += t;
+            }
+            if (ln < kBins) sBin[ln + 1] = v;
+            if (ln == 0) sBin[0] = 0;
+        }
+        __syncthreads();
+        // pass B: write each candidate to its sorted slot
+        auto place = [&](int u, int32_t j, int run, int bin, int rk) {
+            const int32_t l = threadIdx.x + u * kThreads;
+            if (l >= tlen) return;
+            const int slot = sBin[bin] + sCnt[u][wave][bin] + rk;
+            float4 pp = A.pos[j];
+            pp.x += shift_x(j, run);
+            pp.y += R.sy[run];
+            pp.z += R.sz[run];
+            sP[slot] = pp;
+            sV[slot] = A.velrho[j];
+            if (BWD) {
+                float4 ab = A.ace[j];
+                if (run < nbruns) ab.x = ab.y = ab.z = 0.f;
+                sA[slot] = ab;
+            }
+            if (STATS) sSlot[slot] = j;
+            sMap[l] = (uint16_t)slot;
+        };
+        place(0, j0, q0, bn0, rk0);
+        if (STAGE > 1) place(1, j1, q1, bn1, rk1);
+        if (STAGE > 2) place(2, j2, q2, bn2, rk2);
+        if (STAGE > 3) place(3, j3, q3, bn3, rk3);
+        if (threadIdx.x < 2 * kWave) sP[tlen + threadIdx.x] = make_float4(kFar, kFar, kFar, 0.f);
+        __syncthreads();
+
+        // ---- one wavefront per target
+        const int32_t selfbase =
+            FLUID ? __builtin_amdgcn_readfirstlane(R.vstart[R.self_run] - R.s[R.self_run][0]) - tb
+                  : 0;
+        for (int32_t a = tbeg + wave; a < tend; a += kWaves) {
+            const int32_t self_v = FLUID ? selfbase + a : -1;  // staging index of a
+            const bool self_here = FLUID && self_v >= 0 && self_v < tlen;
+            const int32_t self_l = self_here ? (int32_t)sMap[self_v] : 0;
+            float4 pa, va, aa = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (self_here) {
+                pa = sP[self_l];
+                va = sV[self_l];
+                if (BWD) aa = sA[self_l];
+            } else {
+                pa = A.pos[a];
+                va = A.velrho[a];
+                if (BWD && FLUID) aa = A.ace[a];
+            }
+            // t = rho / rho0; the Monaghan factor cbar / rhobar for c = c0 t^3 is
+            // (c0 / rho0) (ta^3 + tb^3) / (ta + tb) = (c0 / rho0) (ta^2 - ta tb + tb^2)
+            const float ta = __builtin_fmaf(va.w, K.inv_rho0, 1.0f);
+            const float ta2 = ta * ta;
+            // forward: Pi_ab = kh (ta^2 - ta tb + tb^2) min(u, 0), u = v.r / (r^2 + eta2),
+            // evaluated as tb (kh tb - kh ta) + kh ta^2
+            const float kta = -K.kh * ta, kta2 = K.kh * ta2;
+            // backward: d(P/rho^2)/drho = c^2 / rho^2 - 2 (P/rho^2) / rho, c = c0 ta^3
+            float dpa = 0.f;
+            if (BWD) {
+                const float inv_ra = __builtin_amdgcn_rcpf(K.rho0 * ta);
+                const float ca = K.c0 * ta2 * ta;
+                dpa = (ca * inv_ra) * (ca * inv_ra) - 2.f * pa.w * inv_ra;
+            }
+            // accumulators: forward (s0..s3 = sums for a.xyz and drho in units of
+            // gs, vmf = max |u|); backward (s0..s2 = xbar, s3 = rhobar, s4..s6 = vbar,
+            // s7 = alphabar)
+            float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f, s4 = 0.f, s5 = 0.f, s6 = 0.f,
+                  s7 = 0.f, vmf = 0.f;
+            unsigned hs = 0;
+            int wp = 0, rp = 0;          // ring write / read counters (wave-uniform)
+            uint32_t raddr = rfirst;     // this lane's ring entry of the next batch
+
+            // one batch: every lane evaluates the pair with the staged entry at
+            // byte offset off
+            auto pair = [&](uint32_t off) {
+                const float4 pb = lds_load4(sPb + off);
+                const float4 vb = lds_load4(sVb + off);
+                const float rx = pa.x - pb.x, ry = pa.y - pb.y, rz = pa.z - pb.z;
+                const float r2 = __builtin_fmaf(rz, rz, __builtin_fmaf(ry, ry, rx * rx));
+                const float r = __builtin_amdgcn_sqrtf(r2);
+                // kernel gradient factor in units of gs: F = gs G (grad_a W = F r_ab)
+                float G, wq = 0.f, qq = 0.f;
+                if (KER == SPH_WENDLAND5) {
+                    wq = __builtin_fmaf(-0.5f * K.inv_h, r, 1.0f);
+                    G = wq * wq * wq;
+                } else {
+                    qq = r * K.inv_h;
+                    const float t = 2.f - qq;
+                    G = qq < 1.f ? __builtin_fmaf(2.25f, qq, -3.f)
+                                 : K.kco * (t * t) * __builtin_amdgcn_rcpf(r);
+                }
+                const float vx = va.x - vb.x, vy = va.y - vb.y, vz = va.z - vb.z;
+                const float vdr = __builtin_fmaf(vz, rz, __builtin_fmaf(vy, ry, vx * rx));
+                if (!BWD) {
+                    s3 = __builtin_fmaf(vdr, G, s3);
+                    if (FLUID) {
+                        const float u = vdr * __builtin_amdgcn_rcpf(r2 + K.eta2);
+                        vmf = fmaxf(vmf, fabsf(u));
+                        const float tb = __builtin_fmaf(vb.w, K.inv_rho0, 1.0f);
+                        const float crk = __builtin_fmaf(tb, __builtin_fmaf(tb, K.kh, kta), kta2);
+                        // P_a/rho_a^2 + P_b/rho_b^2 + Pi_ab
+                        const float sm = __builtin_fmaf(crk, fminf(u, 0.f), pa.w + pb.w);
+                        const float coef = sm * G;
+                        s0 = __builtin_fmaf(coef, rx, s0);
+                        s1 = __builtin_fmaf(coef, ry, s1);
+                        s2 = __builtin_fmaf(coef, rz, s2);
+                    }
+                    if (STATS) hs += (uint32_t)A.ids[sSlot[off >> 4]] * 2654435761u;
+                } else {
+                    const float F = K.gs * G;
+                    // Pair contribution to the loss, symmetric in (a, b):
+                    //   (abar_a - abar_b) . T_ab + (Dbar_a + Dbar_b) S_ab,
+                    //   T_ab = -m s F r_ab, s = P_a/rho_a^2 + P_b/rho_b^2 + Pi_ab,
+                    //   S_ab = m (v_ab . r_ab) F;  its derivatives w.r.t. the gatherer a.
+                    const float4 ab = lds_load4(sAb + off);
+                    const float dax = aa.x - ab.x, day = aa.y - ab.y, daz = aa.z - ab.z;
+                    const float Q = __builtin_fmaf(daz, rz, __builtin_fmaf(day, ry, dax * rx));
+                    const float tb = __builtin_fmaf(vb.w, K.inv_rho0, 1.0f);
+                    const float cr = __builtin_fmaf(tb, tb - ta, ta2);
+                    const float invden = __builtin_amdgcn_rcpf(r2 + K.eta2);
+                    const float mu = K.h * vdr * invden;
+                    const float mneg = fminf(mu, 0.f);
+                    // d/drho_a of s: d(P/rho^2)/drho + dPi/drho_a
+                    const float dpi_dra = K.kpi * K.inv_rho0 * __builtin_fmaf(2.f, ta, -tb) * mneg;
+                    s3 = __builtin_fmaf(-F * Q, dpa + dpi_dra, s3);
+                    if (FLUID) {
+                        // (dF/dr) / r; 0 for the self pair
+                        float Fr;
+                        if (KER == SPH_WENDLAND5) {
+                            Fr = K.kfr * wq * wq * __builtin_amdgcn_rcpf(r);
+                        } else {
+                            const float ir = __builtin_amdgcn_rcpf(r);
+                            Fr = qq < 1.f ? K.kcr_in * ir
+                                          : K.kcr_out * __builtin_fmaf(-qq, qq, 4.f) * (ir * ir * ir);
+                        }
+                        Fr = r2 > 0.f ? Fr : 0.f;
+                        // continuity
+                        const float sD = aa.w + ab.w;
+                        const float c1 = sD * F, c2 = sD * vdr * Fr;
+                        // momentum
+                        const float pi = K.kpi * cr * mneg;
+                        const float sm = pa.w + pb.w + pi;
+                        const float dpi_dmu = mu < 0.f ? K.kpi * cr : 0.f;
+                        const float e1 = F * Q * dpi_dmu;
+                        const float e1h = e1 * K.h * invden;
+                        const float e2 = __builtin_fmaf(-2.f * e1 * invden, mu, sm * Q * Fr);
+                        const float e3 = sm * F;
+                        s0 += __builtin_fmaf(c1, vx, c2 * rx) - __builtin_fmaf(e1h, vx, __builtin_fmaf(e2, rx, e3 * dax));
+                        s1 += __builtin_fmaf(c1, vy, c2 * ry) - __builtin_fmaf(e1h, vy, __builtin_fmaf(e2, ry, e3 * day));
+                        s2 += __builtin_fmaf(c1, vz, c2 * rz) - __builtin_fmaf(e1h, vz, __builtin_fmaf(e2, rz, e3 * daz));
+                        const float g = c1 - e1h;
+                        s4 = __builtin_fmaf(g, rx, s4);
+                        s5 = __builtin_fmaf(g, ry, s5);
+                        s6 = __builtin_fmaf(g, rz, s6);
+                        // alpha: own target term abar_a . dA_a/dalpha, dPi/dalpha = Pi/alpha
+                        const float qa = __builtin_fmaf(aa.z, rz, __builtin_fmaf(aa.y, ry, aa.x * rx));
+                        s7 = __builtin_fmaf(-F * qa, K.kpa * cr * mneg, s7);
+                    }
+                }
+            };
+
+            // test one chunk of 64 staged candidates; survivors go to the ring as
+            // byte offsets of their staged entries, full batches of 64 are
+            // evaluated at once.  The ring holds kRing entries in 256 bytes, so
+            // slot k sits at rbase | (2 k mod 256).
+            auto chunk = [&](const float4 pb, int32_t cb0) {
+                const float rx = pa.x - pb.x, ry = pa.y - pb.y, rz = pa.z - pb.z;
+                const float r2 = __builtin_fmaf(rz, rz, __builtin_fmaf(ry, ry, rx * rx));
+                const bool pass = r2 < K.rc2;
+                const unsigned long long m = ballot(pass);
+                // rank in every lane (no exec-mask switch); rejected lanes write
+                // their own trash slot
+                int rk = (int)lane_rank(m);
+                asm volatile("" : "+v"(rk));
+                const uint32_t w = ((uint32_t)(2 * (wp + rk)) & 0xFEu) | rbase;
+                *(lds_u16 *)(uintptr_t)(pass ? w : taddr) = (uint16_t)(lane16 + ((uint32_t)cb0 << 4));
+                wp += __popcll(m);
+                if (wp - rp >= kWave) {
+                    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                    pair(*(const lds_u16 *)(uintptr_t)raddr);
+                    raddr ^= 2u * kWave;
+                    rp += kWave;
+                }
+            };
+            // the window of x-bins within 2h of the target (conservative: bins
+            // are monotone in x), rounded up to whole chunks of 64; entries past
+            // the window are real candidates or padding and are tested as usual.
+            // Two chunks per iteration, both loaded up front: the second read
+            // ends before tlen + 2 * kWave, inside the padding.
+            // (wave-uniform: every lane holds the same target)
+            const int32_t w0 = __builtin_amdgcn_readfirstlane(sBin[xbin(pa.x - K.xwin)]);
+            const int32_t w1 = __builtin_amdgcn_readfirstlane(sBin[xbin(pa.x + K.xwin) + 1]);
+            const int32_t wend = w0 + ((w1 - w0 + kWave - 1) & ~(kWave - 1));
+            for (int32_t cb0 = w0; cb0 < wend; cb0 += 2 * kWave) {
+                const float4 c0 = sP[cb0 + lane];
+                const float4 c1 = sP[cb0 + kWave + lane];
+                chunk(c0, cb0);
+                if (cb0 + kWave < wend) chunk(c1, cb0 + kWave);
+            }
+            if (wp > rp) {
+                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                if (lane < wp - rp) pair(*(const lds_u16 *)(uintptr_t)raddr);
+            }
+            const int cnt = wp - (self_here ? 1 : 0);
+            pairs_acc += (unsigned long long)cnt;
+
+            // ---- reduce over the wave, write (first tile) or accumulate
+            if (!BWD && FLUID) {
+                // lane l < 4 ends with component l: a.x, a.y, a.z (in units of
+                // -m gs), drho/dt (in units of m gs)
+                const float t = wave_sum4(s0, s1, s2, s3, lane, xa);
+                const float tvm = wave_max_nonneg(vmf, xa) * K.h;
+                unsigned ths = 0;
+                if (STATS) {
+                    ths = wave_sum_u(hs);
+                    if (self_here) ths -= (uint32_t)A.ids[a] * 2654435761u;
+                }
+                if (lane < 4) {
+                    float *o = (float *)A.ace + 4 * (int64_t)a + lane;
+                    float v = (lane < 3 ? -K.mgs : K.mgs) * t;
+                    if (tb == 0) {
+                        v += lane == 0 ? K.gx : lane == 1 ? K.gy : lane == 2 ? K.gz : 0.f;
+                        *o = v;
+                    } else {
+                        *o += v;
+                    }
+                }
+                if (lane == 0) {
+                    A.visc[a] = tb == 0 ? tvm : fmaxf(A.visc[a], tvm);
+                    if (STATS) {
+                        if (tb == 0) {
+                            A.stats[2 * a] = cnt;
+                            A.stats[2 * a + 1] = (int32_t)ths;
+                        } else {
+                            A.stats[2 * a] += cnt;
+                            A.stats[2 * a + 1] = (int32_t)((uint32_t)A.stats[2 * a + 1] + ths);
+                        }
+                    }
+                }
+            } else if (!BWD) {
+                const float tsd = wave_sum(s3);
+                unsigned ths = 0;
+                if (STATS) ths = wave_sum_u(hs);
+                if (lane == 0) {
+                    const float d = K.mgs * tsd;
+                    if (tb == 0) {
+                        A.ace[a] = make_float4(0.f, 0.f, 0.f, d);
+                        A.visc[a] = 0.f;
+                        if (STATS) { A.stats[2 * a] = cnt; A.stats[2 * a + 1] = (int32_t)ths; }
+                    } else {
+                        A.ace[a].w += d;
+                        if (STATS) {
+                            A.stats[2 * a] += cnt;
+                            A.stats[2 * a + 1] = (int32_t)((uint32_t)A.stats[2 * a + 1] + ths);
+                        }
+                    }
+                }
+            } else if (FLUID) {
+                // lane l < 8 ends with s_l: xbar.xyz, rhobar, vbar.xyz, alphabar
+                const float t = wave_sum8(s0, s1, s2, s3, s4, s5, s6, s7, lane, xa);
+                if (lane < 8) {
+                    const float v = K.mass * t;
+                    if (lane < 3) {
+                        ((float *)A.xbar)[4 * (int64_t)a + lane] += v;
+                    } else if (lane < 7) {
+                        ((float *)A.vbar)[4 * (int64_t)a + (lane == 3 ? 3 : lane - 4)] += v;
+                    } else {
+                        A.alpha_part[a] = (tb == 0 ? 0.f : A.alpha_part[a]) + v;
+                    }
+                }
+            } else {
+                const float tr = wave_sum(s3);
+                if (lane == 0) A.vbar[a].w += K.mass * tr;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+template <int KIND, bool STATS, int KER>
+__global__ __launch_bounds__(kThreads) void k_interact(PairConsts K, PairArgs A)
+{
+    using T = KindTraits<KIND>;
+    __shared__ PairLds<T::tile, T::bwd, STATS> S;
+    LaneCtx C;
+    C.lane = threadIdx.x & (kWave - 1);
+    C.wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    uint32_t rbase = lds_addr(&S.sRing[C.wave][0]);
+    C.rfirst = rbase | (2u * C.lane);
     asm volatile("" : "+v"(rbase));  // per-lane copy: one and-or per ring slot
-    const XorAddr xa = xor_addr(lane);
-    uint32_t lane16 = (uint32_t)lane << 4;  // byte offset of this lane's entry in a chunk
+    C.rbase = rbase;
+    C.xa = xor_addr(C.lane);
+    uint32_t lane16 = (uint32_t)C.lane << 4;  // byte offset of this lane's entry in a chunk
     asm volatile("" : "+v"(lane16));
-    const uint32_t taddr = lds_addr(&sTrash[wave][lane]);
-    const uint32_t sPb = lds_addr(sP), sVb = lds_addr(sV), sAb = lds_addr(sA);
-    // Work items: fluid cells are list[info[0] .. info[0] + info[1]); boundary
+    C.lane16 = lane16;
+    C.taddr = lds_addr(&S.sTrash[C.wave][C.lane]);
+    C.sPb = lds_addr(S.sP);
+    C.sVb = lds_addr(S.sV);
+    C.sAb = lds_addr(S.sA);
+
+    // First list: fluid cells are list[info[0] .. info[0] + info[1]); boundary
     // cells with fluid in reach are active[0 .. nactive).  Counts are clamped
     // so that inconsistent inputs can never index outside [0, n).
     int32_t ibase, nitems;
-    if (FLUID) {
+    if (T::fluid) {
         ibase = min(max(A.counts[0], 0), K.n);
         nitems = min(max(A.counts[1], 0), K.n - ibase);
     } else {
         ibase = 0;
         nitems = min(max(A.counts[0], 0), K.n);
     }
-    unsigned long long pairs_acc = 0;  // wave-uniform
+    unsigned long long p1 = 0, p2 = 0;  // wave-uniform pair counts of the two lists
     // XCD-aware dynamic schedule: the work list is cut into kXcds contiguous
     // chunks with one counter each; workgroup b starts on chunk b mod kXcds
     // (the XCD it runs on), so neighbouring cells share that XCD's L2, and
@@ -329,7 +740,6 @@ __global__ __launch_bounds__(kThreads) void k_interact(PairConsts K, PairArgs A)
     // after kXcds exhausted chunks, so the grid always drains.
     const int home = blockIdx.x % kXcds;
     int tries = 0;  // meaningful in thread 0 only
-
     for (;;) {
         if (threadIdx.x == 0) {
             int32_t it = -1;
@@ -344,382 +754,42 @@ __global__ __launch_bounds__(kThreads) void k_interact(PairConsts K, PairArgs A)
                 }
                 ++tries;
             }
-            sItem = it;
+            S.sItem = it;
         }
         __syncthreads();
-        const int32_t item = __builtin_amdgcn_readfirstlane(sItem);
+        const int32_t item = __builtin_amdgcn_readfirstlane(S.sItem);
         if (item < 0) break;
         const int32_t key =
             __builtin_amdgcn_readfirstlane(min(max(A.items[ibase + item], 0), 2 * K.ncell - 1));
-        const int32_t c = FLUID ? max(key - K.ncell, 0) : min(key, K.ncell - 1);
-        const int32_t cx = c % K.nc0, cy = (c / K.nc0) % K.nc1, cz = c / (K.nc0 * K.nc1);
-        const int32_t tbeg = __builtin_amdgcn_readfirstlane(min(max(A.start[key], 0), K.n));
-        const int32_t tend = __builtin_amdgcn_readfirstlane(min(max(A.start[key + 1], tbeg), K.n));
-
-        build_runs<FLUID>(K, A.start, cx, cy, cz, R);
-        const int32_t total = __builtin_amdgcn_readfirstlane(R.total);
-        const int nr = __builtin_amdgcn_readfirstlane(R.nruns);
-        const int nbruns = FLUID ? nr / 2 : 0;  // runs [0, nbruns) hold boundary particles
-
-        for (int32_t tb = 0; tb < max(total, 1); tb += TILE) {
-            const int32_t tlen = max(min(TILE, total - tb), 0);
-            // ---- stage candidates [tb, tb + tlen) into LDS, ordered by the x-bin of
-            //      their position in the target frame (stable in staging order), so
-            //      that each target scans one contiguous window |x_a - x_b| < 2h
-            // locate staging index l: slot j of the sorted state and its run
-            auto locate = [&](int32_t l, int32_t &j, int &run) {
-                const int32_t v = tb + min(l, max(tlen - 1, 0));
-                int lo = 0, hi = nr;  // find r with vstart[r] <= v < vstart[r+1]
-                while (hi - lo > 1) {
-                    const int mid = (lo + hi) >> 1;
-                    if (R.vstart[mid] <= v) lo = mid;
-                    else hi = mid;
-                }
-                j = min(max(R.s[lo][0] + (v - R.vstart[lo]), 0), K.n - 1);
-                run = lo;
-            };
-            // frame shift (k_b - k_a) cell along x, exact
-            auto shift_x = [&](int32_t j, int run) {
-                int ci = 0;
-                for (int i = 1; i < R.ncx[run]; ++i) ci += R.s[run][i] <= j ? 1 : 0;
-                return (float)(R.dx0[run] + ci) * K.cellf;
-            };
-            // rank among the equal x-bins of this wave (stable in lane order)
-            auto rank_round = [&](int u, int bin) {
-                const bool valid = (int32_t)(threadIdx.x + u * kThreads) < tlen;
-                unsigned long long peers = ballot(valid);
-                for (int b = 0; b < kBinBits; ++b) {
-                    const bool bit = (bin >> b) & 1;
-                    const unsigned long long mb = ballot(bit);
-                    peers &= bit ? mb : ~mb;
-                }
-                const int rk = (int)lane_rank(peers);
-                if (valid && rk == 0) sCnt[u][wave][bin] = (uint16_t)__popcll(peers);
-                return rk;
-            };
-            static_assert(STAGE <= 4, "staging rounds");
-            for (int i = threadIdx.x; i < STAGE * kWaves * kBins; i += kThreads)
-                (&sCnt[0][0][0])[i] = 0;
-            // pass A: locate all of this thread's candidates, then one round of loads
-            int32_t j0 = 0, j1 = 0, j2 = 0, j3 = 0;
-            int q0 = 0, q1 = 0, q2 = 0, q3 = 0;
-            locate(threadIdx.x, j0, q0);
-            if (STAGE > 1) locate(threadIdx.x + kThreads, j1, q1);
-            if (STAGE > 2) locate(threadIdx.x + 2 * kThreads, j2, q2);
-            if (STAGE > 3) locate(threadIdx.x + 3 * kThreads, j3, q3);
-            const float x0 = A.pos[j0].x, x1 = STAGE > 1 ? A.pos[j1].x : 0.f,
-                        x2 = STAGE > 2 ? A.pos[j2].x : 0.f, x3 = STAGE > 3 ? A.pos[j3].x : 0.f;
-            const int bn0 = xbin(x0 + shift_x(j0, q0));
-            const int bn1 = STAGE > 1 ? xbin(x1 + shift_x(j1, q1)) : 0;
-            const int bn2 = STAGE > 2 ? xbin(x2 + shift_x(j2, q2)) : 0;
-            const int bn3 = STAGE > 3 ? xbin(x3 + shift_x(j3, q3)) : 0;
-            __syncthreads();
-            const int rk0 = rank_round(0, bn0);
-            const int rk1 = STAGE > 1 ? rank_round(1, bn1) : 0;
-            const int rk2 = STAGE > 2 ? rank_round(2, bn2) : 0;
-            const int rk3 = STAGE > 3 ? rank_round(3, bn3) : 0;
-            __syncthreads();
-            if ((int)threadIdx.x < kBins) {  // per-bin offsets over (round, wave)
-                const int b = threadIdx.x;
-                int run = 0;
-                for (int u = 0; u < STAGE; ++u)
-                    for (int w = 0; w < kWaves; ++w) {
-                        const int cc = sCnt[u][w][b];
-                        sCnt[u][w][b] = (uint16_t)run;
-                        run += cc;
-                    }
-                sBin[b + 1] = run;
+        pair_item<T::first, STATS, KER>(K, A, S, C, key, p1);
+    }
+    if (T::fused) {
+        // second list: active boundary cells through one counter; every
+        // workgroup leaves when the counter passes the count
+        const int32_t n2 = min(max(A.counts2[0], 0), K.n);
+        for (;;) {
+            __syncthreads();  // every thread has read the previous S.sItem
+            if (threadIdx.x == 0) {
+                const int32_t k = atomicAdd(A.queue2, 1);
+                S.sItem = k < n2 ? k : -1;
             }
             __syncthreads();
-            if (threadIdx.x < kWave) {  // bin starts: exclusive scan of the bin totals
-                const int ln = threadIdx.x;
-                int32_t v = ln < kBins ? sBin[ln + 1] : 0;
-                for (int o = 1; o < kWave; o <<= 1) {
-                    const int32_t t = __shfl_up(v, o);
-                    if (ln >= o) v += t;
-                }
-                if (ln < kBins) sBin[ln + 1] = v;
-                if (ln == 0) sBin[0] = 0;
-            }
-            __syncthreads();
-            // pass B: write each candidate to its sorted slot
-            auto place = [&](int u, int32_t j, int run, int bin, int rk) {
-                const int32_t l = threadIdx.x + u * kThreads;
-                if (l >= tlen) return;
-                const int slot = sBin[bin] + sCnt[u][wave][bin] + rk;
-                float4 pp = A.pos[j];
-                pp.x += shift_x(j, run);
-                pp.y += R.sy[run];
-                pp.z += R.sz[run];
-                sP[slot] = pp;
-                sV[slot] = A.velrho[j];
-                if (BWD) {
-                    float4 ab = A.ace[j];
-                    if (run < nbruns) ab.x = ab.y = ab.z = 0.f;
-                    sA[slot] = ab;
-                }
-                if (STATS) sSlot[slot] = j;
-                sMap[l] = (uint16_t)slot;
-            };
-            place(0, j0, q0, bn0, rk0);
-            if (STAGE > 1) place(1, j1, q1, bn1, rk1);
-            if (STAGE > 2) place(2, j2, q2, bn2, rk2);
-            if (STAGE > 3) place(3, j3, q3, bn3, rk3);
-            if (threadIdx.x < 2 * kWave) sP[tlen + threadIdx.x] = make_float4(kFar, kFar, kFar, 0.f);
-            __syncthreads();
-
-            // ---- one wavefront per target
-            const int32_t selfbase =
-                FLUID ? __builtin_amdgcn_readfirstlane(R.vstart[R.self_run] - R.s[R.self_run][0]) - tb
-                      : 0;
-            for (int32_t a = tbeg + wave; a < tend; a += kWaves) {
-                const int32_t self_v = FLUID ? selfbase + a : -1;  // staging index of a
-                const bool self_here = FLUID && self_v >= 0 && self_v < tlen;
-                const int32_t self_l = self_here ? (int32_t)sMap[self_v] : 0;
-                float4 pa, va, aa = make_float4(0.f, 0.f, 0.f, 0.f);
-                if (self_here) {
-                    pa = sP[self_l];
-                    va = sV[self_l];
-                    if (BWD) aa = sA[self_l];
-                } else {
-                    pa = A.pos[a];
-                    va = A.velrho[a];
-                    if (BWD && FLUID) aa = A.ace[a];
-                }
-                // t = rho / rho0; the Monaghan factor cbar / rhobar for c = c0 t^3 is
-                // (c0 / rho0) (ta^3 + tb^3) / (ta + tb) = (c0 / rho0) (ta^2 - ta tb + tb^2)
-                const float ta = __builtin_fmaf(va.w, K.inv_rho0, 1.0f);
-                const float ta2 = ta * ta;
-                // forward: Pi_ab = kh (ta^2 - ta tb + tb^2) min(u, 0), u = v.r / (r^2 + eta2),
-                // evaluated as tb (kh tb - kh ta) + kh ta^2
-                const float kta = -K.kh * ta, kta2 = K.kh * ta2;
-                // backward: d(P/rho^2)/drho = c^2 / rho^2 - 2 (P/rho^2) / rho, c = c0 ta^3
-                float dpa = 0.f;
-                if (BWD) {
-                    const float inv_ra = __builtin_amdgcn_rcpf(K.rho0 * ta);
-                    const float ca = K.c0 * ta2 * ta;
-                    dpa = (ca * inv_ra) * (ca * inv_ra) - 2.f * pa.w * inv_ra;
-                }
-                // accumulators: forward (s0..s3 = sums for a.xyz and drho in units of
-                // gs, vmf = max |u|); backward (s0..s2 = xbar, s3 = rhobar, s4..s6 = vbar,
-                // s7 = alphabar)
-                float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f, s4 = 0.f, s5 = 0.f, s6 = 0.f,
-                      s7 = 0.f, vmf = 0.f;
-                unsigned hs = 0;
-                int wp = 0, rp = 0;          // ring write / read counters (wave-uniform)
-                uint32_t raddr = rfirst;     // this lane's ring entry of the next batch
-
-                // one batch: every lane evaluates the pair with the staged entry at
-                // byte offset off
-                auto pair = [&](uint32_t off) {
-                    const float4 pb = lds_load4(sPb + off);
-                    const float4 vb = lds_load4(sVb + off);
-                    const float rx = pa.x - pb.x, ry = pa.y - pb.y, rz = pa.z - pb.z;
-                    const float r2 = __builtin_fmaf(rz, rz, __builtin_fmaf(ry, ry, rx * rx));
-                    const float r = __builtin_amdgcn_sqrtf(r2);
-                    // kernel gradient factor in units of gs: F = gs G (grad_a W = F r_ab)
-                    float G, wq = 0.f, qq = 0.f;
-                    if (KER == SPH_WENDLAND5) {
-                        wq = __builtin_fmaf(-0.5f * K.inv_h, r, 1.0f);
-                        G = wq * wq * wq;
-                    } else {
-                        qq = r * K.inv_h;
-                        const float t = 2.f - qq;
-                        G = qq < 1.f ? __builtin_fmaf(2.25f, qq, -3.f)
-                                     : K.kco * (t * t) * __builtin_amdgcn_rcpf(r);
-                    }
-                    const float vx = va.x - vb.x, vy = va.y - vb.y, vz = va.z - vb.z;
-                    const float vdr = __builtin_fmaf(vz, rz, __builtin_fmaf(vy, ry, vx * rx));
-                    if (!BWD) {
-                        s3 = __builtin_fmaf(vdr, G, s3);
-                        if (FLUID) {
-                            const float u = vdr * __builtin_amdgcn_rcpf(r2 + K.eta2);
-                            vmf = fmaxf(vmf, fabsf(u));
-                            const float tb = __builtin_fmaf(vb.w, K.inv_rho0, 1.0f);
-                            const float crk = __builtin_fmaf(tb, __builtin_fmaf(tb, K.kh, kta), kta2);
-                            // P_a/rho_a^2 + P_b/rho_b^2 + Pi_ab
-                            const float sm = __builtin_fmaf(crk, fminf(u, 0.f), pa.w + pb.w);
-                            const float coef = sm * G;
-                            s0 = __builtin_fmaf(coef, rx, s0);
-                            s1 = __builtin_fmaf(coef, ry, s1);
-                            s2 = __builtin_fmaf(coef, rz, s2);
-                        }
-                        if (STATS) hs += (uint32_t)A.ids[sSlot[off >> 4]] * 2654435761u;
-                    } else {
-                        const float F = K.gs * G;
-                        // Pair contribution to the loss, symmetric in (a, b):
-                        //   (abar_a - abar_b) . T_ab + (Dbar_a + Dbar_b) S_ab,
-                        //   T_ab = -m s F r_ab, s = P_a/rho_a^2 + P_b/rho_b^2 + Pi_ab,
-                        //   S_ab = m (v_ab . r_ab) F;  its derivatives w.r.t. the gatherer a.
-                        const float4 ab = lds_load4(sAb + off);
-                        const float dax = aa.x - ab.x, day = aa.y - ab.y, daz = aa.z - ab.z;
-                        const float Q = __builtin_fmaf(daz, rz, __builtin_fmaf(day, ry, dax * rx));
-                        const float tb = __builtin_fmaf(vb.w, K.inv_rho0, 1.0f);
-                        const float cr = __builtin_fmaf(tb, tb - ta, ta2);
-                        const float invden = __builtin_amdgcn_rcpf(r2 + K.eta2);
-                        const float mu = K.h * vdr * invden;
-                        const float mneg = fminf(mu, 0.f);
-                        // d/drho_a of s: d(P/rho^2)/drho + dPi/drho_a
-                        const float dpi_dra = K.kpi * K.inv_rho0 * __builtin_fmaf(2.f, ta, -tb) * mneg;
-                        s3 = __builtin_fmaf(-F * Q, dpa + dpi_dra, s3);
-                        if (FLUID) {
-                            // (dF/dr) / r; 0 for the self pair
-                            float Fr;
-                            if (KER == SPH_WENDLAND5) {
-                                Fr = K.kfr * wq * wq * __builtin_amdgcn_rcpf(r);
-                            } else {
-                                const float ir = __builtin_amdgcn_rcpf(r);
-                                Fr = qq < 1.f ? K.kcr_in * ir
-                                              : K.kcr_out * __builtin_fmaf(-qq, qq, 4.f) * (ir * ir * ir);
-                            }
-                            Fr = r2 > 0.f ? Fr : 0.f;
-                            // continuity
-                            const float sD = aa.w + ab.w;
-                            const float c1 = sD * F, c2 = sD * vdr * Fr;
-                            // momentum
-                            const float pi = K.kpi * cr * mneg;
-                            const float sm = pa.w + pb.w + pi;
-                            const float dpi_dmu = mu < 0.f ? K.kpi * cr : 0.f;
-                            const float e1 = F * Q * dpi_dmu;
-                            const float e1h = e1 * K.h * invden;
-                            const float e2 = __builtin_fmaf(-2.f * e1 * invden, mu, sm * Q * Fr);
-                            const float e3 = sm * F;
-                            s0 += __builtin_fmaf(c1, vx, c2 * rx) - __builtin_fmaf(e1h, vx, __builtin_fmaf(e2, rx, e3 * dax));
-                            s1 += __builtin_fmaf(c1, vy, c2 * ry) - __builtin_fmaf(e1h, vy, __builtin_fmaf(e2, ry, e3 * day));
-                            s2 += __builtin_fmaf(c1, vz, c2 * rz) - __builtin_fmaf(e1h, vz, __builtin_fmaf(e2, rz, e3 * daz));
-                            const float g = c1 - e1h;
-                            s4 = __builtin_fmaf(g, rx, s4);
-                            s5 = __builtin_fmaf(g, ry, s5);
-                            s6 = __builtin_fmaf(g, rz, s6);
-                            // alpha: own target term abar_a . dA_a/dalpha, dPi/dalpha = Pi/alpha
-                            const float qa = __builtin_fmaf(aa.z, rz, __builtin_fmaf(aa.y, ry, aa.x * rx));
-                            s7 = __builtin_fmaf(-F * qa, K.kpa * cr * mneg, s7);
-                        }
-                    }
-                };
-
-                // test one chunk of 64 staged candidates; survivors go to the ring as
-                // byte offsets of their staged entries, full batches of 64 are
-                // evaluated at once.  The ring holds kRing entries in 256 bytes, so
-                // slot k sits at rbase | (2 k mod 256).
-                auto chunk = [&](const float4 pb, int32_t cb0) {
-                    const float rx = pa.x - pb.x, ry = pa.y - pb.y, rz = pa.z - pb.z;
-                    const float r2 = __builtin_fmaf(rz, rz, __builtin_fmaf(ry, ry, rx * rx));
-                    const bool pass = r2 < K.rc2;
-                    const unsigned long long m = ballot(pass);
-                    // rank in every lane (no exec-mask switch); rejected lanes write
-                    // their own trash slot
-                    int rk = (int)lane_rank(m);
-                    asm volatile("" : "+v"(rk));
-                    const uint32_t w = ((uint32_t)(2 * (wp + rk)) & 0xFEu) | rbase;
-                    *(lds_u16 *)(uintptr_t)(pass ? w : taddr) = (uint16_t)(lane16 + ((uint32_t)cb0 << 4));
-                    wp += __popcll(m);
-                    if (wp - rp >= kWave) {
-                        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-                        pair(*(const lds_u16 *)(uintptr_t)raddr);
-                        raddr ^= 2u * kWave;
-                        rp += kWave;
-                    }
-                };
-                // the window of x-bins within 2h of the target (conservative: bins
-                // are monotone in x), rounded up to whole chunks of 64; entries past
-                // the window are real candidates or padding and are tested as usual.
-                // Two chunks per iteration, both loaded up front: the second read
-                // ends before tlen + 2 * kWave, inside the padding.
-                // (wave-uniform: every lane holds the same target)
-                const int32_t w0 = __builtin_amdgcn_readfirstlane(sBin[xbin(pa.x - K.xwin)]);
-                const int32_t w1 = __builtin_amdgcn_readfirstlane(sBin[xbin(pa.x + K.xwin) + 1]);
-                const int32_t wend = w0 + ((w1 - w0 + kWave - 1) & ~(kWave - 1));
-                for (int32_t cb0 = w0; cb0 < wend; cb0 += 2 * kWave) {
-                    const float4 c0 = sP[cb0 + lane];
-                    const float4 c1 = sP[cb0 + kWave + lane];
-                    chunk(c0, cb0);
-                    if (cb0 + kWave < wend) chunk(c1, cb0 + kWave);
-                }
-                if (wp > rp) {
-                    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-                    if (lane < wp - rp) pair(*(const lds_u16 *)(uintptr_t)raddr);
-                }
-                const int cnt = wp - (self_here ? 1 : 0);
-                pairs_acc += (unsigned long long)cnt;
-
-                // ---- reduce over the wave, write (first tile) or accumulate
-                if (!BWD && FLUID) {
-                    // lane l < 4 ends with component l: a.x, a.y, a.z (in units of
-                    // -m gs), drho/dt (in units of m gs)
-                    const float t = wave_sum4(s0, s1, s2, s3, lane, xa);
-                    const float tvm = wave_max_nonneg(vmf, xa) * K.h;
-                    unsigned ths = 0;
-                    if (STATS) {
-                        ths = wave_sum_u(hs);
-                        if (self_here) ths -= (uint32_t)A.ids[a] * 2654435761u;
-                    }
-                    if (lane < 4) {
-                        float *o = (float *)A.ace + 4 * (int64_t)a + lane;
-                        float v = (lane < 3 ? -K.mgs : K.mgs) * t;
-                        if (tb == 0) {
-                            v += lane == 0 ? K.gx : lane == 1 ? K.gy : lane == 2 ? K.gz : 0.f;
-                            *o = v;
-                        } else {
-                            *o += v;
-                        }
-                    }
-                    if (lane == 0) {
-                        A.visc[a] = tb == 0 ? tvm : fmaxf(A.visc[a], tvm);
-                        if (STATS) {
-                            if (tb == 0) {
-                                A.stats[2 * a] = cnt;
-                                A.stats[2 * a + 1] = (int32_t)ths;
-                            } else {
-                                A.stats[2 * a] += cnt;
-                                A.stats[2 * a + 1] = (int32_t)((uint32_t)A.stats[2 * a + 1] + ths);
-                            }
-                        }
-                    }
-                } else if (!BWD) {
-                    const float tsd = wave_sum(s3);
-                    unsigned ths = 0;
-                    if (STATS) ths = wave_sum_u(hs);
-                    if (lane == 0) {
-                        const float d = K.mgs * tsd;
-                        if (tb == 0) {
-                            A.ace[a] = make_float4(0.f, 0.f, 0.f, d);
-                            A.visc[a] = 0.f;
-                            if (STATS) { A.stats[2 * a] = cnt; A.stats[2 * a + 1] = (int32_t)ths; }
-                        } else {
-                            A.ace[a].w += d;
-                            if (STATS) {
-                                A.stats[2 * a] += cnt;
-                                A.stats[2 * a + 1] = (int32_t)((uint32_t)A.stats[2 * a + 1] + ths);
-                            }
-                        }
-                    }
-                } else if (FLUID) {
-                    // lane l < 8 ends with s_l: xbar.xyz, rhobar, vbar.xyz, alphabar
-                    const float t = wave_sum8(s0, s1, s2, s3, s4, s5, s6, s7, lane, xa);
-                    if (lane < 8) {
-                        const float v = K.mass * t;
-                        if (lane < 3) {
-                            ((float *)A.xbar)[4 * (int64_t)a + lane] += v;
-                        } else if (lane < 7) {
-                            ((float *)A.vbar)[4 * (int64_t)a + (lane == 3 ? 3 : lane - 4)] += v;
-                        } else {
-                            A.alpha_part[a] = (tb == 0 ? 0.f : A.alpha_part[a]) + v;
-                        }
-                    }
-                } else {
-                    const float tr = wave_sum(s3);
-                    if (lane == 0) A.vbar[a].w += K.mass * tr;
-                }
-            }
-            __syncthreads();
+            const int32_t item = __builtin_amdgcn_readfirstlane(S.sItem);
+            if (item < 0) break;
+            const int32_t key =
+                __builtin_amdgcn_readfirstlane(min(max(A.items2[item], 0), 2 * K.ncell - 1));
+            pair_item<T::second, STATS, KER>(K, A, S, C, key, p2);
         }
     }
-    if (A.npairs && lane == 0 && pairs_acc) atomicAdd(A.npairs, pairs_acc);
+    if (A.npairs && C.lane == 0) {
+        if (p1) atomicAdd(A.npairs + (T::fluid ? 0 : 1), p1);
+        if (p2) atomicAdd(A.npairs + 1, p2);
+    }
 }
 
 // Boundary cells: those with fluid particles in their stencil go to the work
-// list of the B-F kernel; the others have no neighbours and get zero outputs.
+// list of the B-F pass; the others have no neighbours and get zero outputs,
+// as do excluded particles (forward only: ace != NULL).
 __global__ void k_bound_filter(PairConsts K, const int32_t *__restrict__ start,
                                const int32_t *__restrict__ list, const int32_t *__restrict__ info,
                                int32_t *__restrict__ active, int32_t *__restrict__ nactive,
@@ -751,6 +821,15 @@ __global__ void k_bound_filter(PairConsts K, const int32_t *__restrict__ start,
             }
         }
     }
+    if (ace) {  // excluded particles (the tail of the sorted state) get zero outputs
+        const int32_t nex = min(max(info[2], 0), K.n);
+        for (int32_t i = K.n - nex + blockIdx.x * blockDim.x + threadIdx.x; i < K.n;
+             i += gridDim.x * blockDim.x) {
+            ace[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+            visc[i] = 0.f;
+            if (stats) { stats[2 * i] = 0; stats[2 * i + 1] = 0; }
+        }
+    }
 }
 
 __global__ void k_zero_counters(int32_t *q, int count)
@@ -758,18 +837,6 @@ __global__ void k_zero_counters(int32_t *q, int count)
     if ((int)threadIdx.x < count) q[threadIdx.x] = 0;
 }
 
-// Excluded particles (the tail of the sorted state) get zero outputs.
-__global__ void k_zero_excluded(int32_t n, const int32_t *__restrict__ info, float4 *__restrict__ ace,
-                                float *__restrict__ visc, int32_t *__restrict__ stats)
-{
-    const int32_t nex = min(max(info[2], 0), n);
-    for (int32_t i = n - nex + blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += gridDim.x * blockDim.x) {
-        ace[i] = make_float4(0.f, 0.f, 0.f, 0.f);
-        visc[i] = 0.f;
-        if (stats) { stats[2 * i] = 0; stats[2 * i + 1] = 0; }
-    }
-}
 
 static PairConsts pair_consts(const sph_grid *g, const sph_params *p, int32_t n)
 {
@@ -841,7 +908,7 @@ static hipError_t launch_one(const PairConsts &K, const PairArgs &A, hipStream_t
 template <int KIND>
 static hipError_t launch_kind(const PairConsts &K, const PairArgs &A, bool stats, hipStream_t s)
 {
-    constexpr bool fwd = KIND == kFwdFluid || KIND == kFwdBound;
+    constexpr bool fwd = KIND == kFwdFluid || KIND == kFwdBound || KIND == kFwdAll;
     if (K.kernel == SPH_CUBIC_SPLINE) {
         if (fwd && stats) return launch_one<KIND, fwd, SPH_CUBIC_SPLINE>(K, A, s);
         return launch_one<KIND, false, SPH_CUBIC_SPLINE>(K, A, s);
@@ -865,6 +932,9 @@ static PairArgs base_args(const sph_state *st, const sph_cells *cells)
     A.vbar = nullptr;
     A.alpha_part = nullptr;
     A.queue = nullptr;
+    A.items2 = nullptr;
+    A.counts2 = nullptr;
+    A.queue2 = nullptr;
     A.npairs = nullptr;
     A.stats = nullptr;
     return A;
@@ -882,23 +952,32 @@ hipError_t launch_interact(const sph_grid *g, const sph_params *p, const sph_sta
     A.visc = visc;
     A.npairs = npairs;
     A.stats = nbr_stats;
-    // counters: [0, 8) fluid queues, [8, 16) boundary queues, [16] active boundary cells
+    // counters: [0, 8) first-list queues, [8, 16) boundary queues of a separate
+    // boundary launch or [8] the boundary counter of the fused launch, [16]
+    // active boundary cells
+    const bool stats = nbr_stats != nullptr;
+    k_zero_counters<<<1, 64, 0, s>>>(w.counters, 17);
+    if (parts & SPH_PI_BOUNDARY)
+        k_bound_filter<<<256, 256, 0, s>>>(K, cells->start, cells->list, cells->info, w.active,
+                                           w.counters + 16, (float4 *)ace, visc, nbr_stats);
+    if (parts == SPH_PI_ALL) {
+        A.queue = w.counters;
+        A.items2 = w.active;
+        A.counts2 = w.counters + 16;
+        A.queue2 = w.counters + 8;
+        return launch_kind<kFwdAll>(K, A, stats, s);
+    }
     hipError_t e = hipSuccess;
     if (parts & SPH_PI_FLUID) {
-        k_zero_counters<<<1, 64, 0, s>>>(w.counters + 0, kXcds);
-        A.queue = w.counters + 0;
-        e = launch_kind<kFwdFluid>(K, A, nbr_stats != nullptr, s);
+        A.queue = w.counters;
+        e = launch_kind<kFwdFluid>(K, A, stats, s);
         if (e != hipSuccess) return e;
     }
     if (parts & SPH_PI_BOUNDARY) {
-        k_zero_counters<<<1, 64, 0, s>>>(w.counters + 8, kXcds + 1);
-        k_zero_excluded<<<64, 256, 0, s>>>(st->n, cells->info, (float4 *)ace, visc, nbr_stats);
-        k_bound_filter<<<256, 256, 0, s>>>(K, cells->start, cells->list, cells->info, w.active,
-                                           w.counters + 16, (float4 *)ace, visc, nbr_stats);
         A.items = w.active;
         A.counts = w.counters + 16;
         A.queue = w.counters + 8;
-        e = launch_kind<kFwdBound>(K, A, nbr_stats != nullptr, s);
+        e = launch_kind<kFwdBound>(K, A, stats, s);
     }
     return e;
 }
@@ -951,18 +1030,16 @@ hipError_t launch_interact_backward(const sph_grid *g, const sph_params *p, cons
     A.xbar = (float4 *)pos_bar;
     A.vbar = (float4 *)velrho_bar;
     A.alpha_part = w.alpha_part;
-    // counters: [24, 32) fluid queues, [32, 40) boundary queues, [40] active cells
-    k_zero_counters<<<1, 64, 0, s>>>(w.counters + 24, 2 * kXcds + 1);
-    A.queue = w.counters + 24;
-    hipError_t e = launch_kind<kBwdFluid>(K, A, false, s);
-    if (e != hipSuccess) return e;
+    // counters: [24, 32) fluid queues, [32] boundary counter, [40] active cells
+    k_zero_counters<<<1, 64, 0, s>>>(w.counters + 24, 17);
     // boundary gatherers: only cells with fluid in reach have non-zero terms
     k_bound_filter<<<256, 256, 0, s>>>(K, cells->start, cells->list, cells->info, w.active,
                                        w.counters + 40, nullptr, nullptr, nullptr);
-    A.items = w.active;
-    A.counts = w.counters + 40;
-    A.queue = w.counters + 32;
-    e = launch_kind<kBwdBound>(K, A, false, s);
+    A.queue = w.counters + 24;
+    A.items2 = w.active;
+    A.counts2 = w.counters + 40;
+    A.queue2 = w.counters + 32;
+    hipError_t e = launch_kind<kBwdAll>(K, A, false, s);
     if (e != hipSuccess) return e;
     int nblk = (int)(((int64_t)st->n + kReduceThreads - 1) / kReduceThreads);
     if (nblk > kReduceBlocksMax) nblk = kReduceBlocksMax;

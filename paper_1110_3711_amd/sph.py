@@ -138,6 +138,8 @@ def sph_build_cells(grid, src, dst, cells, perm, ws, dev_status, stream=None):
 
 def sph_interact(grid, params, state, cells, ace, visc, npairs, ws, nbr_stats=None,
                  parts=SPH_PI_ALL, stream=None):
+    if npairs is not None and npairs.numel() < 2:
+        raise SphError("npairs needs 2 entries (fluid-target, boundary-target pairs)")
     _check(load().sph_interact(C.byref(grid), C.byref(params), C.byref(state), C.byref(cells),
                                int(parts), _ptr(ace), _ptr(visc), _ptr(npairs), _ptr(nbr_stats),
                                _ptr(ws), ws.numel(), _stream(stream)), "sph_interact")
@@ -246,7 +248,7 @@ class Simulation:
         self.perm = torch.empty(max(n, 1), dtype=torch.int32, device=self.device)
         self.ace = torch.empty((max(n, 1), 4), dtype=torch.float32, device=self.device)
         self.visc = torch.empty(max(n, 1), dtype=torch.float32, device=self.device)
-        self.npairs = torch.zeros(1, dtype=torch.int64, device=self.device)
+        self.npairs = torch.zeros(2, dtype=torch.int64, device=self.device)  # fluid, boundary targets
         self.dt = torch.zeros(1, dtype=torch.float64, device=self.device)
         self.status = torch.zeros(1, dtype=torch.int32, device=self.device)
         self.step_index = 0

@@ -19,4 +19,5 @@ from .dambreak import (  # noqa: F401
     dam_break,
     named_case,
     physics,
+    refine,
 )

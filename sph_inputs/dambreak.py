@@ -202,6 +202,45 @@ def blob(n_side: int, dp: float, seed: int, vel_sigma: float = 0.5, jitter: floa
                   meta={"dp": dp, "seed": seed, "n_side": n_side})
 
 
+def refine(x_fluid, v_fluid, rho_fluid, dp: float, factor: int = 8, seed: int = SEED_BASE + 3,
+           jitter: float = 0.05, tank=(0.8, 0.4, 0.4), alpha: float = 0.1, kernel: int = 0,
+           name: str = "refined") -> Layout:
+    """Clustered layout from a coarse fluid state (e.g. a dam-break snapshot):
+    every fluid particle becomes ``factor^3`` children on a sub-lattice of
+    spacing ``dp/factor`` centred on it, inheriting its velocity and density,
+    with seeded uniform jitter of +-``jitter`` times the new spacing; the tank
+    walls are regenerated at the new spacing.  Parent cubes overlap or leave
+    gaps wherever the coarse particles were not on their lattice, which gives
+    uneven density.  Only the positions are built here: no kernel, pair
+    term or integrator is evaluated."""
+    x_fluid = np.asarray(x_fluid, dtype=np.float64).reshape(-1, 3)
+    v_fluid = np.asarray(v_fluid, dtype=np.float64).reshape(-1, 3)
+    rho_fluid = np.asarray(rho_fluid, dtype=np.float64).ravel()
+    d = dp / factor
+    sub = (np.arange(factor) + 0.5) * d - 0.5 * dp            # child offsets from the parent
+    gz, gy, gx = np.meshgrid(sub, sub, sub, indexing="ij")
+    off = np.stack([gx.ravel(), gy.ravel(), gz.ravel()], axis=1)  # X fastest
+    m = off.shape[0]
+    flu = (x_fluid[:, None, :] + off[None, :, :]).reshape(-1, 3)
+    if jitter:
+        rng = np.random.default_rng(seed)
+        flu += rng.uniform(-jitter * d, jitter * d, size=flu.shape)
+    ntx, nty, ntz = (int(round(t / d)) for t in tank)
+    bnd = _tank_walls(ntx, nty, ntz, d)
+    ph = physics(d, alpha=alpha, kernel=kernel)
+    x = np.concatenate([bnd, flu], axis=0)
+    nb = bnd.shape[0]
+    n = x.shape[0]
+    v = np.zeros((n, 3), dtype=np.float64)
+    v[nb:] = np.repeat(v_fluid, m, axis=0)
+    rho = np.full(n, ph.rho0, dtype=np.float64)
+    rho[nb:] = np.repeat(rho_fluid, m)
+    lo = np.array([-2 * d, -2 * d, -2 * d])
+    hi = np.array([ntx * d + 2 * d, nty * d + 2 * d, 2.0 * ntz * d])
+    return Layout(name=name, x=x, v=v, rho=rho, nb=nb, phys=ph, lo=lo, hi=hi,
+                  meta={"dp": d, "seed": seed, "factor": factor, "parents": x_fluid.shape[0]})
+
+
 CASES = {
     "cfg1": Case("cfg1", 0.01, 100,
                  "3D dam break, 8,000 fluid + 27,232 boundary particles (dp = 0.01 m)"),

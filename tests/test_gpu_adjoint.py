@@ -205,3 +205,30 @@ def test_rollout_gradient_cfg4_short(ora):
     assert ga == pytest.approx(fa, rel=1e-3)
     assert gv[0] == pytest.approx(fv[0], rel=1e-3)
     torch.cuda.synchronize()
+
+
+@pytest.mark.timeout(1500)
+def test_rollout_gradient_cfg4_full(ora):
+    """The differentiable-rollout workload at full length: cfg4 layout, K = 200
+    steps, checkpoint every 20, each side with its own CFL time steps (frozen
+    for the gradient); alpha and one seeded v0 direction vs central FD of the
+    FP64 oracle rollout."""
+    lay = named_case("cfg4")
+    K, C = 200, 20
+    rng = np.random.default_rng(11103711 + 4)
+    target = lay.x[lay.nb:].mean(0) + rng.uniform(-0.01, 0.01, 3)
+    u_dirs = [rng.normal(size=(lay.nf, 3))]
+    print(f"rollout cfg4 n={lay.n} K={K} C={C}", flush=True)
+    ga, gv, roll = _gpu_grad(lay, K, C, None, target, u_dirs)
+    gpu_dts = roll.dts.cpu().numpy()
+    S = ora.State(lay)
+    dts = S.run(K)
+    print(f"  dt: gpu {gpu_dts[0]:.6e}..{gpu_dts[-1]:.6e}, oracle {dts[0]:.6e}..{dts[-1]:.6e}",
+          flush=True)
+    assert np.allclose(gpu_dts, dts, rtol=1e-3)
+    fa, fv = _oracle_fd(ora, lay, dts, target, u_dirs)
+    print(f"  alpha: gpu {ga:.6e} fd {fa:.6e} rel {abs(ga - fa) / abs(fa):.2e}; "
+          f"v0: gpu {gv[0]:.6e} fd {fv[0]:.6e} rel {abs(gv[0] - fv[0]) / abs(fv[0]):.2e}",
+          flush=True)
+    assert ga == pytest.approx(fa, rel=1e-3)
+    assert gv[0] == pytest.approx(fv[0], rel=1e-3)

@@ -62,7 +62,7 @@ def test_neighbour_sets_bit_exact(ora, nsub):
     s = sim.by_id(st.view(-1, 2))
     assert np.array_equal(s[:, 0], cnt)
     assert np.array_equal(s[:, 1].view(np.uint32), hs)
-    assert int(sim.npairs.item()) == tot
+    assert int(sim.npairs.sum().item()) == tot
 
 
 @pytest.mark.parametrize("nsub", [1, 2])
