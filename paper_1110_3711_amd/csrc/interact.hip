@@ -293,12 +293,16 @@ struct PairLds {
     float4 sA[BWD ? TILE : 1];              // backward: (abar, Dbar), abar = 0 on boundary
     alignas(256) uint16_t sRing[kWaves][kRing];  // 256 bytes per wave
     uint16_t sTrash[kWaves][kWave];         // rejected candidates land here
-    uint16_t sMap[TILE];                    // staging index -> sorted slot
+    union {
+        uint16_t sMap[TILE];                // fluid targets: staging index -> sorted slot
+        float4 sTgt[TILE / 8];              // boundary targets: (pos, velrho) of the first
+    };                                      //   TILE / 16 targets of the cell
     uint16_t sCnt[STAGE][kWaves][kBins];
     int32_t sBin[kBins + 1];                // first sorted slot of each x-bin
     int32_t sSlot[STATS ? TILE : 1];        // candidate slot (diagnostics only)
     RunTable R;
     int32_t sItem;
+    int32_t sKind;                          // fused launches: 0 fluid item, 1 boundary item
 };
 
 // per-lane constants: LDS byte addresses of this wave's ring (256-aligned),
@@ -382,6 +386,13 @@ __device__ __forceinline__ void pair_item(const PairConsts &K, const PairArgs &A
             return rk;
         };
         static_assert(STAGE <= 4, "staging rounds");
+        // boundary targets are not among the (fluid) candidates: stage the
+        // cell's first kTgt targets with the candidates
+        constexpr int32_t kTgt = TILE / 16;
+        if (!FLUID && tb == 0 && (int32_t)threadIdx.x < min(tend - tbeg, kTgt)) {
+            S.sTgt[2 * threadIdx.x] = A.pos[tbeg + threadIdx.x];
+            S.sTgt[2 * threadIdx.x + 1] = A.velrho[tbeg + threadIdx.x];
+        }
         for (int i = threadIdx.x; i < STAGE * kWaves * kBins; i += kThreads)
             (&sCnt[0][0][0])[i] = 0;
         // pass A: locate all of this thread's candidates, then one round of loads
@@ -443,7 +454,7 @@ __device__ __forceinline__ void pair_item(const PairConsts &K, const PairArgs &A
                 sA[slot] = ab;
             }
             if (STATS) sSlot[slot] = j;
-            sMap[l] = (uint16_t)slot;
+            if (FLUID) sMap[l] = (uint16_t)slot;
         };
         place(0, j0, q0, bn0, rk0);
         if (STAGE > 1) place(1, j1, q1, bn1, rk1);
@@ -465,6 +476,9 @@ __device__ __forceinline__ void pair_item(const PairConsts &K, const PairArgs &A
                 pa = sP[self_l];
                 va = sV[self_l];
                 if (BWD) aa = sA[self_l];
+            } else if (!FLUID && a - tbeg < kTgt) {
+                pa = S.sTgt[2 * (a - tbeg)];
+                va = S.sTgt[2 * (a - tbeg) + 1];
             } else {
                 pa = A.pos[a];
                 va = A.velrho[a];
@@ -736,46 +750,65 @@ __global__ __launch_bounds__(kThreads) void k_interact(PairConsts K, PairArgs A)
     // XCD-aware dynamic schedule: the work list is cut into kXcds contiguous
     // chunks with one counter each; workgroup b starts on chunk b mod kXcds
     // (the XCD it runs on), so neighbouring cells share that XCD's L2, and
-    // moves to the next chunk when one is exhausted.  Every workgroup gives up
-    // after kXcds exhausted chunks, so the grid always drains.
+    // moves to the next chunk when one is exhausted.  Fused launches interleave
+    // the second list (one counter): after every `mix` items of the first list
+    // a workgroup takes one of the second, so its short, latency-bound items
+    // overlap with the compute-bound ones instead of forming the tail; once the
+    // first list is exhausted the second is drained.  The counters only grow,
+    // so every workgroup leaves once both lists are exhausted.
+    const int32_t n2 = T::fused ? min(max(A.counts2[0], 0), K.n) : 0;
+    const int32_t mix = nitems / (n2 + 1);
     const int home = blockIdx.x % kXcds;
-    int tries = 0;  // meaningful in thread 0 only
+    int tries = 0;       // exhausted chunks of the first list (thread 0 only)
+    int32_t since = 0;   // first-list items since the last second-list item (thread 0)
+    bool done2 = !T::fused;
     for (;;) {
         if (threadIdx.x == 0) {
             int32_t it = -1;
-            while (tries < kXcds) {
+            int kind = 0;
+            if (!done2 && since >= mix) {
+                const int32_t k = atomicAdd(A.queue2, 1);
+                if (k < n2) {
+                    it = k;
+                    kind = 1;
+                    since = 0;
+                } else {
+                    done2 = true;
+                }
+            }
+            while (it < 0 && tries < kXcds) {
                 const int x = (home + tries) % kXcds;
                 const int32_t lo = (int32_t)(((int64_t)nitems * x) / kXcds);
                 const int32_t hi = (int32_t)(((int64_t)nitems * (x + 1)) / kXcds);
                 const int32_t k = atomicAdd(A.queue + x, 1);
                 if (k < hi - lo) {
                     it = lo + k;
+                    ++since;
                     break;
                 }
                 ++tries;
             }
+            if (it < 0 && !done2) {
+                const int32_t k = atomicAdd(A.queue2, 1);
+                if (k < n2) {
+                    it = k;
+                    kind = 1;
+                } else {
+                    done2 = true;
+                }
+            }
             S.sItem = it;
+            S.sKind = kind;
         }
         __syncthreads();
         const int32_t item = __builtin_amdgcn_readfirstlane(S.sItem);
+        const int kind = __builtin_amdgcn_readfirstlane(S.sKind);
         if (item < 0) break;
-        const int32_t key =
-            __builtin_amdgcn_readfirstlane(min(max(A.items[ibase + item], 0), 2 * K.ncell - 1));
-        pair_item<T::first, STATS, KER>(K, A, S, C, key, p1);
-    }
-    if (T::fused) {
-        // second list: active boundary cells through one counter; every
-        // workgroup leaves when the counter passes the count
-        const int32_t n2 = min(max(A.counts2[0], 0), K.n);
-        for (;;) {
-            __syncthreads();  // every thread has read the previous S.sItem
-            if (threadIdx.x == 0) {
-                const int32_t k = atomicAdd(A.queue2, 1);
-                S.sItem = k < n2 ? k : -1;
-            }
-            __syncthreads();
-            const int32_t item = __builtin_amdgcn_readfirstlane(S.sItem);
-            if (item < 0) break;
+        if (!T::fused || kind == 0) {
+            const int32_t key = __builtin_amdgcn_readfirstlane(
+                min(max(A.items[ibase + item], 0), 2 * K.ncell - 1));
+            pair_item<T::first, STATS, KER>(K, A, S, C, key, p1);
+        } else {
             const int32_t key =
                 __builtin_amdgcn_readfirstlane(min(max(A.items2[item], 0), 2 * K.ncell - 1));
             pair_item<T::second, STATS, KER>(K, A, S, C, key, p2);

@@ -211,8 +211,10 @@ def refine(x_fluid, v_fluid, rho_fluid, dp: float, factor: int = 8, seed: int = 
     with seeded uniform jitter of +-``jitter`` times the new spacing; the tank
     walls are regenerated at the new spacing.  Parent cubes overlap or leave
     gaps wherever the coarse particles were not on their lattice, which gives
-    uneven density.  Only the positions are built here: no kernel, pair
-    term or integrator is evaluated."""
+    uneven density.  The domain box is the coarse case's (2 coarse spacings
+    around the tank, twice its height), the box the coarse state lived in, so
+    children of particles near a wall stay inside it.  Only the positions are
+    built here: no kernel, pair term or integrator is evaluated."""
     x_fluid = np.asarray(x_fluid, dtype=np.float64).reshape(-1, 3)
     v_fluid = np.asarray(v_fluid, dtype=np.float64).reshape(-1, 3)
     rho_fluid = np.asarray(rho_fluid, dtype=np.float64).ravel()
@@ -235,8 +237,8 @@ def refine(x_fluid, v_fluid, rho_fluid, dp: float, factor: int = 8, seed: int = 
     v[nb:] = np.repeat(v_fluid, m, axis=0)
     rho = np.full(n, ph.rho0, dtype=np.float64)
     rho[nb:] = np.repeat(rho_fluid, m)
-    lo = np.array([-2 * d, -2 * d, -2 * d])
-    hi = np.array([ntx * d + 2 * d, nty * d + 2 * d, 2.0 * ntz * d])
+    lo = np.array([-2 * dp, -2 * dp, -2 * dp])
+    hi = np.array([ntx * d + 2 * dp, nty * d + 2 * dp, 2.0 * ntz * d])
     return Layout(name=name, x=x, v=v, rho=rho, nb=nb, phys=ph, lo=lo, hi=hi,
                   meta={"dp": d, "seed": seed, "factor": factor, "parents": x_fluid.shape[0]})
 

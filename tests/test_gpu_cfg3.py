@@ -41,6 +41,7 @@ def cfg3(ora):
     lay = refine(S.x[f][keep], S.v[f][keep], S.rho[f][keep], lay1.meta["dp"], 8,
                  seed=SEED_BASE + 3, name="cfg3")
     assert lay.nf == 4096000 and lay.nb == 1651232
+    assert ora.in_domain(lay.x, lay.lo, lay.hi).all()
     return lay
 
 
@@ -86,6 +87,7 @@ def _policy_errors(ora, lay, tgt, label):
     res = {}
     # (i) cell + FP32 offset
     ace, visc, npairs, cnt, gt = _gpu_forces(lay, lay.x, stats=True)
+    assert ora.in_domain(lay.x, lay.lo, lay.hi).all()
     res["i_true"] = _errors(ace, visc, ref, rvisc, tgt, lay.nb)
     xq, vq, rq, exq, _, _ = oracle_view(ora, lay.x, lay.v, lay.rho, lay.phys.rho0, gt, lay.lo,
                                         lay.hi)

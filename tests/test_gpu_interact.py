@@ -116,3 +116,30 @@ def test_determinism(ora):
     sim.interact()
     torch.cuda.synchronize()
     assert torch.equal(a1, sim.ace) and torch.equal(v1, sim.visc)
+
+
+def test_split_parts_match_fused_launch(ora):
+    """SPH_PI_FLUID then SPH_PI_BOUNDARY (two launches) and SPH_PI_ALL (one
+    fused launch) give bitwise identical outputs and the same pair counts."""
+    import torch
+
+    from paper_1110_3711_amd import sph
+
+    lay = dam_break(0.01, 11103711 + 1, vel_sigma=0.2, vel_seed=78)
+    print("interact split vs fused cfg1+v", flush=True)
+    sim = sph.Simulation(lay, nsub=1)
+    sim.build_cells()
+    st_a = torch.zeros(2 * lay.n, dtype=torch.int32, device=sim.device)
+    np_a = torch.zeros(2, dtype=torch.int64, device=sim.device)
+    sim.interact(stats=st_a, parts=sph.SPH_PI_ALL, npairs=np_a)
+    ace_a, visc_a = sim.ace.clone(), sim.visc.clone()
+    sim.ace.fill_(7.0)
+    sim.visc.fill_(7.0)
+    st_s = torch.zeros_like(st_a)
+    np_s = torch.zeros(2, dtype=torch.int64, device=sim.device)
+    sim.interact(stats=st_s, parts=sph.SPH_PI_FLUID, npairs=np_s)
+    sim.interact(stats=st_s, parts=sph.SPH_PI_BOUNDARY, npairs=np_s)
+    torch.cuda.synchronize()
+    assert torch.equal(ace_a, sim.ace) and torch.equal(visc_a, sim.visc)
+    assert torch.equal(st_a, st_s)
+    assert torch.equal(np_a, np_s) and int(np_a[1]) > 0
