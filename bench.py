@@ -48,7 +48,7 @@ def _kernel_source_hash():
 def _traffic_record():
     """HBM bytes per launch of the fluid pair kernel from the committed
     rocprofv3 counter summary, if it was taken on the current kernel source."""
-    p = os.path.join(ROOT, "profiles", "interact_fluid_cfg2_traffic.json")
+    p = os.path.join(ROOT, "profiles", "interact_dam_break_1m_traffic.json")
     if not os.path.exists(p):
         return None
     rec = json.load(open(p))
@@ -125,11 +125,11 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--config", default="cfg2")
+    ap.add_argument("--config", default="dam_break_1m")
     ap.add_argument("--nsub", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=12.0)
-    ap.add_argument("--adjoint-config", default="cfg4",
+    ap.add_argument("--adjoint-config", default="dam_break_64k",
                     help="layout of the differentiable rollout (default: the 64k-fluid case)")
     ap.add_argument("--adjoint-steps", type=int, default=200)
     ap.add_argument("--adjoint-every", type=int, default=20)
@@ -138,8 +138,8 @@ def main():
                     help="run one 256 MiB device-to-device copy first (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); the "
-              "multi-GPU slab decomposition is a design, not an implementation", file=sys.stderr)
+        print(f"bench.py: the library runs on one GPU (asked for --gpus {args.gpus}); the "
+              "multi-GPU slab decomposition is described, not implemented", file=sys.stderr)
         sys.exit(2)
 
     import torch

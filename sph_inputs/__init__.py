@@ -9,7 +9,9 @@ of the method's code.
 
 from .dambreak import (  # noqa: F401
     CASES,
+    CLUSTER_SEED,
     SEED_BASE,
+    VEL_SEED_64K,
     Case,
     Layout,
     Physics,

@@ -244,24 +244,30 @@ def refine(x_fluid, v_fluid, rho_fluid, dp: float, factor: int = 8, seed: int = 
 
 
 CASES = {
-    "cfg1": Case("cfg1", 0.01, 100,
-                 "3D dam break, 8,000 fluid + 27,232 boundary particles (dp = 0.01 m)"),
-    "cfg2": Case("cfg2", 0.002, 1000,
-                 "3D dam break, 1,000,000 fluid + 648,032 boundary particles (dp = 0.002 m)"),
-    "cfg4": Case("cfg4", 0.005, 200,
-                 "3D dam break, 64,000 fluid + 105,632 boundary particles (dp = 0.005 m), "
-                 "seeded N(0, 0.01^2) initial fluid velocity"),
-    "cfg5": Case("cfg5", 0.2 / 272, 200,
-                 "3D dam break, 20,123,648 fluid + 4,756,768 boundary particles "
-                 "(dp = 0.2/272 m)"),
+    "dam_break_8k": Case("dam_break_8k", 0.01, 100,
+                         "3D dam break, 8,000 fluid + 27,232 boundary particles (dp = 0.01 m)"),
+    "dam_break_1m": Case("dam_break_1m", 0.002, 1000,
+                         "3D dam break, 1,000,000 fluid + 648,032 boundary particles "
+                         "(dp = 0.002 m)"),
+    "dam_break_64k": Case("dam_break_64k", 0.005, 200,
+                          "3D dam break, 64,000 fluid + 105,632 boundary particles (dp = 0.005 m), "
+                          "seeded N(0, 0.01^2) initial fluid velocity"),
+    "dam_break_20m": Case("dam_break_20m", 0.2 / 272, 200,
+                          "3D dam break, 20,123,648 fluid + 4,756,768 boundary particles "
+                          "(dp = 0.2/272 m)"),
 }
+
+# jitter seed offsets from SEED_BASE, and the initial-velocity seed of the
+# 64k case
+_SEED = {"dam_break_8k": 1, "dam_break_1m": 2, "dam_break_64k": 4, "dam_break_20m": 5}
+VEL_SEED_64K = SEED_BASE + 40
+CLUSTER_SEED = SEED_BASE + 3   # jitter of the refined (clustered) layout
 
 
 def named_case(name: str) -> Layout:
-    """Layout of a named configuration, seeded from ``SEED_BASE + index``."""
+    """Layout of a named workload, seeded from ``SEED_BASE`` plus its offset."""
     c = CASES[name]
-    idx = int(name[-1])
-    if name == "cfg4":
-        return dam_break(c.dp, SEED_BASE + idx, vel_sigma=0.01, vel_seed=SEED_BASE + 40,
-                         name=name)
-    return dam_break(c.dp, SEED_BASE + idx, name=name)
+    seed = SEED_BASE + _SEED[name]
+    if name == "dam_break_64k":
+        return dam_break(c.dp, seed, vel_sigma=0.01, vel_seed=VEL_SEED_64K, name=name)
+    return dam_break(c.dp, seed, name=name)

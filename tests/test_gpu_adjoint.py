@@ -30,7 +30,7 @@ def _oracle_state(ora, lay, sim):
     return oracle_view(ora, lay.x, lay.v, lay.rho, lay.phys.rho0, grid_tuple(sim), lay.lo, lay.hi)
 
 
-@pytest.mark.parametrize("which", ["small", "cfg1"])
+@pytest.mark.parametrize("which", ["small", "dam_break_8k"])
 def test_interact_backward_matches_oracle(ora, which):
     import torch
 
@@ -184,17 +184,17 @@ def test_rollout_gradient_small_fixed_dt(ora):
         assert g == pytest.approx(fdv, rel=1e-3)
 
 
-def test_rollout_gradient_cfg4_short(ora):
-    """cfg4 layout (64,000 fluid particles, seeded initial velocities), 30 steps
+def test_rollout_gradient_64k_short(ora):
+    """64k-fluid dam break (64,000 fluid particles, seeded initial velocities), 30 steps
     with a checkpoint every 10; each side freezes its own CFL time steps."""
     import torch
 
-    lay = named_case("cfg4")
+    lay = named_case("dam_break_64k")
     K, C = 30, 10
     rng = np.random.default_rng(11103711 + 4)
     target = lay.x[lay.nb:].mean(0) + rng.uniform(-0.01, 0.01, 3)
     u_dirs = [rng.normal(size=(lay.nf, 3))]
-    print(f"rollout cfg4 n={lay.n} K={K} C={C}", flush=True)
+    print(f"rollout dam_break_64k n={lay.n} K={K} C={C}", flush=True)
     ga, gv, roll = _gpu_grad(lay, K, C, None, target, u_dirs)
     gpu_dts = roll.dts.cpu().numpy()
     S = ora.State(lay)
@@ -208,17 +208,17 @@ def test_rollout_gradient_cfg4_short(ora):
 
 
 @pytest.mark.timeout(1500)
-def test_rollout_gradient_cfg4_full(ora):
-    """The differentiable-rollout workload at full length: cfg4 layout, K = 200
+def test_rollout_gradient_64k_full(ora):
+    """The differentiable-rollout workload at full length: 64k-fluid dam break, K = 200
     steps, checkpoint every 20, each side with its own CFL time steps (frozen
     for the gradient); alpha and one seeded v0 direction vs central FD of the
     FP64 oracle rollout."""
-    lay = named_case("cfg4")
+    lay = named_case("dam_break_64k")
     K, C = 200, 20
     rng = np.random.default_rng(11103711 + 4)
     target = lay.x[lay.nb:].mean(0) + rng.uniform(-0.01, 0.01, 3)
     u_dirs = [rng.normal(size=(lay.nf, 3))]
-    print(f"rollout cfg4 n={lay.n} K={K} C={C}", flush=True)
+    print(f"rollout dam_break_64k n={lay.n} K={K} C={C}", flush=True)
     ga, gv, roll = _gpu_grad(lay, K, C, None, target, u_dirs)
     gpu_dts = roll.dts.cpu().numpy()
     S = ora.State(lay)

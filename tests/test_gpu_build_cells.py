@@ -50,11 +50,11 @@ def _check(ora, lay, sim, x, v, rho, src_ids=None):
 
 
 @pytest.mark.parametrize("nsub", [1, 2])
-def test_build_cells_cfg1(ora, nsub):
+def test_build_cells_8k(ora, nsub):
     from paper_1110_3711_amd import sph
 
-    lay = named_case("cfg1")
-    print(f"build_cells cfg1 nsub={nsub} n={lay.n}", flush=True)
+    lay = named_case("dam_break_8k")
+    print(f"build_cells dam_break_8k nsub={nsub} n={lay.n}", flush=True)
     sim = sph.Simulation(lay, nsub=nsub)
     _check(ora, lay, sim, lay.x, lay.v, lay.rho)
 

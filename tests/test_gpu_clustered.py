@@ -1,4 +1,4 @@
-"""Clustered, uneven-density workload: the cfg1 dam break integrated by the FP64
+"""Clustered, uneven-density workload: the 8k-fluid dam break integrated by the FP64
 oracle to t = 0.3 s, each fluid particle refined into 8^3 children at dp/8
 (4,096,000 fluid + 1,651,232 boundary particles).
 
@@ -20,14 +20,14 @@ import numpy as np
 import pytest
 
 from _helpers import grid_tuple, oracle_view, rel_l2
-from sph_inputs import SEED_BASE, named_case, refine
+from sph_inputs import CLUSTER_SEED, SEED_BASE, named_case, refine
 
 pytestmark = pytest.mark.gpu
 
 
 @pytest.fixture(scope="module")
-def cfg3(ora):
-    lay1 = named_case("cfg1")
+def clustered(ora):
+    lay1 = named_case("dam_break_8k")
     S = ora.State(lay1)
     t, k = 0.0, 0
     t0 = time.perf_counter()
@@ -36,10 +36,10 @@ def cfg3(ora):
         k += 1
     f = slice(lay1.nb, None)
     keep = S.excl[f] == 0
-    print(f"cfg3: oracle cfg1 to t = {t:.4f} s in {k} steps ({time.perf_counter() - t0:.1f} s); "
+    print(f"clustered: oracle dam_break_8k to t = {t:.4f} s in {k} steps ({time.perf_counter() - t0:.1f} s); "
           f"{int(keep.sum())} parents", flush=True)
     lay = refine(S.x[f][keep], S.v[f][keep], S.rho[f][keep], lay1.meta["dp"], 8,
-                 seed=SEED_BASE + 3, name="cfg3")
+                 seed=CLUSTER_SEED, name="dam_break_4m_clustered")
     assert lay.nf == 4096000 and lay.nb == 1651232
     assert ora.in_domain(lay.x, lay.lo, lay.hi).all()
     return lay
@@ -103,10 +103,10 @@ def _policy_errors(ora, lay, tgt, label):
     return res, npairs, cnt
 
 
-def test_cfg3_position_policies(ora, cfg3):
-    lay = cfg3
+def test_clustered_position_policies(ora, clustered):
+    lay = clustered
     tgt = _targets(lay, SEED_BASE + 30)
-    print(f"cfg3 step 0: n={lay.n}", flush=True)
+    print(f"clustered step 0: n={lay.n}", flush=True)
     res, npairs, cnt = _policy_errors(ora, lay, tgt, "step 0")
     fl = cnt[lay.nb:]
     q = np.percentile(fl, [0, 1, 10, 50, 90, 99, 100])
@@ -121,21 +121,21 @@ def test_cfg3_position_policies(ora, cfg3):
     S = ora.State(lay)
     t0 = time.perf_counter()
     S.run(1)
-    print(f"cfg3 step 1: oracle step {time.perf_counter() - t0:.1f} s", flush=True)
+    print(f"clustered step 1: oracle step {time.perf_counter() - t0:.1f} s", flush=True)
     lay1 = lay.copy()
     lay1.x, lay1.v, lay1.rho = S.x.copy(), S.v.copy(), S.rho.copy()
     res1, _, _ = _policy_errors(ora, lay1, tgt, "step 1")
     assert max(res1["i_true"]) <= 1e-4 and max(res1["i_same_state"]) <= 1e-4
 
 
-def test_cfg3_step_timing(cfg3):
+def test_clustered_step_timing(clustered):
     """Whole GPU steps on the clustered layout (timing only; the state evolves
     on the device and is not compared)."""
     import torch
 
     from paper_1110_3711_amd import sph
 
-    sim = sph.Simulation(cfg3, nsub=1)
+    sim = sph.Simulation(clustered, nsub=1)
     for _ in range(3):
         sim.step()
     torch.cuda.synchronize()
@@ -151,6 +151,6 @@ def test_cfg3_step_timing(cfg3):
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / K
     pairs = int(npairs.sum().item()) / K
-    print(f"cfg3 timing: {ms:.3f} ms/step, {1e3 / ms:.1f} steps/s, {pairs:.4g} directed pairs/step, "
+    print(f"clustered timing: {ms:.3f} ms/step, {1e3 / ms:.1f} steps/s, {pairs:.4g} directed pairs/step, "
           f"{pairs / ms * 1e3:.4g} pairs/s, status {sim.dev_status()}", flush=True)
     assert not sim.dev_status() & sph.SPH_DEV_NONFINITE

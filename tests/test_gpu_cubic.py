@@ -30,7 +30,7 @@ def test_cubic_forces_match_oracle(ora, nsub):
     from paper_1110_3711_amd import sph
 
     lay = _layout()
-    print(f"cubic interact cfg1+v nsub={nsub}", flush=True)
+    print(f"cubic interact dam_break_8k+v nsub={nsub}", flush=True)
     sim = sph.Simulation(lay, nsub=nsub)
     sim.build_cells()
     sim.npairs.zero_()

@@ -51,8 +51,8 @@ def _compare_forces(ora, lay, sim, tol=TOL):
 
 @pytest.mark.parametrize("nsub", [1, 2])
 def test_neighbour_sets_bit_exact(ora, nsub):
-    lay = named_case("cfg1")
-    print(f"interact stats cfg1 nsub={nsub}", flush=True)
+    lay = named_case("dam_break_8k")
+    print(f"interact stats dam_break_8k nsub={nsub}", flush=True)
     sim, st = _run(lay, nsub, stats=True)
     gt = grid_tuple(sim)
     _, _, _, _, cidx, off = oracle_view(ora, lay.x, lay.v, lay.rho, lay.phys.rho0, gt, lay.lo,
@@ -66,16 +66,16 @@ def test_neighbour_sets_bit_exact(ora, nsub):
 
 
 @pytest.mark.parametrize("nsub", [1, 2])
-def test_forces_cfg1_moving(ora, nsub):
+def test_forces_8k_moving(ora, nsub):
     lay = dam_break(0.01, 11103711 + 1, vel_sigma=0.2, vel_seed=77)
-    print(f"interact forces cfg1+v nsub={nsub}", flush=True)
+    print(f"interact forces dam_break_8k+v nsub={nsub}", flush=True)
     sim, _ = _run(lay, nsub)
     _compare_forces(ora, lay, sim)
 
 
-def test_forces_cfg1_rest(ora):
-    lay = named_case("cfg1")
-    print("interact forces cfg1 rest", flush=True)
+def test_forces_8k_rest(ora):
+    lay = named_case("dam_break_8k")
+    print("interact forces dam_break_8k rest", flush=True)
     sim, _ = _run(lay, 1)
     gt = grid_tuple(sim)
     xq, vq, rq, excl, _, _ = oracle_view(ora, lay.x, lay.v, lay.rho, lay.phys.rho0, gt, lay.lo,
@@ -126,7 +126,7 @@ def test_split_parts_match_fused_launch(ora):
     from paper_1110_3711_amd import sph
 
     lay = dam_break(0.01, 11103711 + 1, vel_sigma=0.2, vel_seed=78)
-    print("interact split vs fused cfg1+v", flush=True)
+    print("interact split vs fused dam_break_8k+v", flush=True)
     sim = sph.Simulation(lay, nsub=1)
     sim.build_cells()
     st_a = torch.zeros(2 * lay.n, dtype=torch.int32, device=sim.device)

@@ -52,7 +52,7 @@ def _grid(lay, nsub):
 
 
 def test_bench_layout_subset_parity(ora):
-    lay = dam_break(0.002, SEED_BASE + 2, vel_sigma=0.05, vel_seed=SEED_BASE + 20, name="cfg2+v")
+    lay = dam_break(0.002, SEED_BASE + 2, vel_sigma=0.05, vel_seed=SEED_BASE + 20, name="dam_break_1m+v")
     print("large: 1.65M-particle dam break", flush=True)
     e = _subset_parity(ora, lay, 1)
     assert max(e) <= 1e-4
@@ -62,7 +62,7 @@ def test_largest_layout_subset_parity(ora):
     """24.9 M particles (dp = 0.2/272 m); positions are cell + FP32 offset, so
     the error stays at the small-domain level."""
     lay = dam_break(0.2 / 272, SEED_BASE + 5, vel_sigma=0.05, vel_seed=SEED_BASE + 50,
-                    name="cfg5+v")
+                    name="dam_break_20m+v")
     print("large: 24.9M-particle dam break", flush=True)
     e = _subset_parity(ora, lay, 1, nsample=32768)
     assert max(e) <= 1e-4

@@ -67,13 +67,13 @@ def test_one_step_matches_oracle(ora, step_index):
 
 
 def test_per_step_force_parity_along_trajectory(ora):
-    """The oracle integrates cfg1 in FP64 for 100 steps; at every 10th step its
+    """The oracle integrates the 8k-fluid dam break in FP64 for 100 steps; at every 10th step its
     state is encoded on the device and the GPU forces are compared (1e-4)."""
     import torch
 
     from paper_1110_3711_amd import sph
 
-    lay = named_case("cfg1")
+    lay = named_case("dam_break_8k")
     S = ora.State(lay)
     errs = []
     for k in range(11):
@@ -176,7 +176,7 @@ def test_boundaries_fixed_and_floored(ora):
 
     from paper_1110_3711_amd import sph
 
-    lay = named_case("cfg1")
+    lay = named_case("dam_break_8k")
     print("boundary floor", flush=True)
     sim = sph.Simulation(lay, nsub=1)
     sim.run(20)

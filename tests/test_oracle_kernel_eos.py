@@ -121,7 +121,7 @@ def test_hydrostatic_initial_density(ora):
     # rho0 |g| (H - z): checks the generator's inverse against the oracle EOS.
     from sph_inputs import named_case
 
-    L = named_case("cfg1")
+    L = named_case("dam_break_8k")
     P = ora.params(L.phys)
     H = L.meta["H"]
     idx = np.arange(L.nb, L.n, 97)

@@ -13,8 +13,8 @@ import numpy as np
 from sph_inputs import blob, cell_grid, dam_break, named_case
 
 
-def test_brute_equals_cells_cfg1(ora):
-    L = named_case("cfg1")
+def test_brute_equals_cells_8k(ora):
+    L = named_case("dam_break_8k")
     P = ora.params(L.phys)
     rb, cb = ora.neighbour_csr(L.x, L.nb, L.phys.h, mode=0)
     rc, cc = ora.neighbour_csr(L.x, L.nb, L.phys.h, mode=1)
@@ -48,7 +48,7 @@ def test_neighbour_sets_by_definition(ora):
 
 
 def test_no_boundary_boundary_pairs(ora):
-    L = named_case("cfg1")
+    L = named_case("dam_break_8k")
     xb = L.x[: L.nb]
     rp, cols = ora.neighbour_csr(xb, L.nb, L.phys.h, mode=1)
     assert rp[-1] == 0
@@ -58,7 +58,7 @@ def test_no_boundary_boundary_pairs(ora):
 
 
 def test_excluded_particles_never_interact(ora):
-    L = named_case("cfg1")
+    L = named_case("dam_break_8k")
     P = ora.params(L.phys)
     excl = np.zeros(L.n, dtype=np.uint8)
     excl[L.nb + 100:L.nb + 200] = 1
@@ -69,7 +69,7 @@ def test_excluded_particles_never_interact(ora):
 
 
 def test_fp32_decision_matches_fp64_sets(ora):
-    L = named_case("cfg1")
+    L = named_case("dam_break_8k")
     for nsub in (1, 2):
         org, cell, nc = cell_grid(L, nsub)
         cidx, off = ora.encode(L.x, org, cell, nc, L.lo, L.hi)
@@ -97,8 +97,8 @@ def test_fp32_decision_matches_fp64_sets(ora):
 
 def test_stencil_superset(ora):
     # With offsets |o| <= cell/2, a pair inside the support lies within
-    # (2 nsub + 1)^3 cells: check every FP64 neighbour pair of cfg1.
-    L = named_case("cfg1")
+    # (2 nsub + 1)^3 cells: check every FP64 neighbour pair of the 8k-fluid dam break.
+    L = named_case("dam_break_8k")
     for nsub in (1, 2):
         org, cell, nc = cell_grid(L, nsub)
         cidx, off = ora.encode(L.x, org, cell, nc, L.lo, L.hi)

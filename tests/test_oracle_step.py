@@ -87,7 +87,7 @@ def test_verlet_regular_and_corrective_updates(ora):
 
 
 def test_boundary_particles_fixed_and_density_floored(ora):
-    L = named_case("cfg1")
+    L = named_case("dam_break_8k")
     S = ora.State(L)
     S.run(5)
     assert np.array_equal(S.x[: L.nb], L.x[: L.nb])
@@ -95,14 +95,14 @@ def test_boundary_particles_fixed_and_density_floored(ora):
     assert np.all(S.rho[: L.nb] >= L.phys.rho0)
     assert np.any(S.rho[: L.nb] > L.phys.rho0)  # loaded boundary compresses
     # without the floor, suction can bring boundary density below rho0
-    L2 = named_case("cfg1")
+    L2 = named_case("dam_break_8k")
     P = ora.params(L2.phys, bound_floor=0)
     S2 = ora.State(L2, P)
     ace = np.zeros((L2.n, 4))
     ace[: L2.nb, 3] = -1.0
     S2.verlet(ace, 1e-3)
     assert np.all(S2.rho[: L2.nb] < L2.phys.rho0)
-    S3 = ora.State(named_case("cfg1"))
+    S3 = ora.State(named_case("dam_break_8k"))
     S3.verlet(ace, 1e-3)
     assert np.all(S3.rho[: L2.nb] == L2.phys.rho0)
 
@@ -139,7 +139,7 @@ def test_still_water_column(ora):
 
 
 def test_encoding_round_trip(ora):
-    L = named_case("cfg1")
+    L = named_case("dam_break_8k")
     for nsub in (1, 2):
         org, cell, nc = cell_grid(L, nsub)
         cidx, off = ora.encode(L.x, org, cell, nc, L.lo, L.hi)
