@@ -53,7 +53,7 @@
 extern "C" {
 #endif
 
-#define SPH_ABI_VERSION 1
+#define SPH_ABI_VERSION 2 /* 2: npairs of sph_interact has two entries */
 #define SPH_API __attribute__((visibility("default")))
 #define SPH_EXCLUDED INT32_MAX /* cell index of a particle outside the domain */
 

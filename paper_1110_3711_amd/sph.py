@@ -21,7 +21,7 @@ SPH_DEV_OUT_OF_GRID, SPH_DEV_NONFINITE = 1, 2
 SPH_FIXED_DT, SPH_ADJOINT = 1, 2
 SPH_PI_FLUID, SPH_PI_BOUNDARY, SPH_PI_ALL = 1, 2, 3
 SPH_EXCLUDED = 2**31 - 1
-ABI_VERSION = 1
+ABI_VERSION = 2
 
 EXPORTS = ["sph_workspace_bytes", "sph_abi_version", "sph_encode", "sph_decode",
            "sph_build_cells", "sph_interact", "sph_step", "sph_interact_backward",
