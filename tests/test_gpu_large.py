@@ -66,3 +66,26 @@ def test_largest_layout_subset_parity(ora):
     print("large: 24.9M-particle dam break", flush=True)
     e = _subset_parity(ora, lay, 1, nsample=32768)
     assert max(e) <= 1e-4
+
+
+def test_bench_layout_parity_along_oracle_trajectory(ora):
+    """The bench workload integrated by the FP64 oracle (its own CFL time
+    steps); at steps 10 and 20 its state is encoded on the device and the GPU
+    forces are compared on a seeded 65,536-target subset."""
+    import time
+
+    lay = dam_break(0.002, SEED_BASE + 2, vel_sigma=0.05, vel_seed=SEED_BASE + 20,
+                    name="dam_break_1m+v")
+    S = ora.State(lay)
+    done = 0
+    for k in (10, 20):
+        t0 = time.perf_counter()
+        S.run(k - done)
+        done = k
+        L = lay.copy()
+        L.x, L.v, L.rho = S.x.copy(), S.v.copy(), S.rho.copy()
+        L.name = f"dam_break_1m+v step {k}"
+        print(f"large trajectory: oracle at step {k} ({time.perf_counter() - t0:.1f} s)",
+              flush=True)
+        e = _subset_parity(ora, L, 1, seed=k)
+        assert max(e) <= 1e-4
