@@ -25,28 +25,23 @@ from . import sph
 
 
 class _Tape:
-    """Device copies kept for one replayed step."""
+    """Device buffers of one replayed step, allocated once and reused by every
+    segment: the sorted state before the Verlet update (written directly by
+    sph_build_cells), its cell arrays and permutation, and its (a, D)."""
 
     def __init__(self, sim):
-        a = sim.a
-        self.cell = a.cell.clone()
-        self.pos = a.pos.clone()
-        self.velrho = a.velrho.clone()
-        self.velrho_prev = a.velrho_prev.clone()
-        self.id = a.id.clone()
-        self.perm = sim.perm.clone()
-        self.start = sim.start.clone()
-        self.list = sim.list.clone()
-        self.info = sim.info.clone()
-        self.ace = None
+        import torch
 
-    def state(self, n, nb) -> sph.State:
-        s = sph.State()
-        s.n, s.nb = n, nb
-        s.cell, s.pos = self.cell.data_ptr(), self.pos.data_ptr()
-        s.velrho, s.velrho_prev = self.velrho.data_ptr(), self.velrho_prev.data_ptr()
-        s.id = self.id.data_ptr()
-        return s
+        n, dev = sim.n, sim.device
+        self.st = sph.DeviceState(n, sim.nb, dev)
+        self.start = torch.empty(2 * sim.ncell + 2, dtype=torch.int32, device=dev)
+        self.list = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
+        self.info = torch.zeros(4, dtype=torch.int32, device=dev)
+        self.perm = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
+        self.ace = torch.empty((max(n, 1), 4), dtype=torch.float32, device=dev)
+
+    def state(self) -> sph.State:
+        return self.st.c()
 
     def cells(self) -> sph.Cells:
         c = sph.Cells()
@@ -84,6 +79,7 @@ class Rollout:
                 raise ValueError("dts must have one entry per step")
         self.dts = torch.zeros(self.K, dtype=torch.float64, device=self.device)
         self.ckpt = {}
+        self.tapes = []
         self.alpha = float(layout.phys.alpha)
 
     # -- state helpers
@@ -96,24 +92,36 @@ class Rollout:
         for dst, src in zip((a.cell, a.pos, a.velrho, a.velrho_prev, a.id), snap):
             dst.copy_(src)
 
-    def _one_step(self, n, record):
+    def _one_step(self, n, tape=None):
+        """One step from the state in sim.a.  With a tape, the sorted state,
+        cell arrays, permutation and (a, D) of the step are kept in it and
+        the time step is the recorded (or given) one."""
         sim = self.sim
-        sim.build_cells()
-        tape = _Tape(sim) if record else None
-        sim.interact()
-        if tape is not None:
-            tape.ace = sim.ace.clone()
+        fixed = self.fixed_dts if self.fixed_dts is not None else (self.dts if tape is not None else None)
+        if tape is None:
+            sim.build_cells()
+            sim.interact()
+            ace = sim.ace
+        else:
+            sph.sph_build_cells(sim.grid, sim.a.c(), tape.state(), tape.cells(), tape.perm,
+                                sim.ws, sim.status)
+            sph.sph_interact(sim.grid, sim.params, tape.state(), tape.cells(), tape.ace,
+                             sim.visc, sim.npairs, sim.ws)
+            # the Verlet update works in place: give it a copy, keep the tape
+            a, t = sim.a, tape.st
+            for dst, src in ((a.cell, t.cell), (a.pos, t.pos), (a.velrho, t.velrho),
+                             (a.velrho_prev, t.velrho_prev), (a.id, t.id)):
+                dst.copy_(src)
+            ace = tape.ace
         sim.step_index = n
-        if record or self.fixed_dts is not None:
-            src = self.fixed_dts if self.fixed_dts is not None else self.dts
-            sim.dt.copy_(src[n:n + 1])
-            sph.sph_step(sim.grid, sim.params, sim.a.c(), sim.ace, sim.visc, sim.dt, n,
+        if fixed is not None:
+            sim.dt.copy_(fixed[n:n + 1])
+            sph.sph_step(sim.grid, sim.params, sim.a.c(), ace, sim.visc, sim.dt, n,
                          sph.SPH_FIXED_DT, sim.ws, sim.status)
         else:
-            sph.sph_step(sim.grid, sim.params, sim.a.c(), sim.ace, sim.visc, sim.dt, n, 0,
-                         sim.ws, sim.status)
+            sph.sph_step(sim.grid, sim.params, sim.a.c(), ace, sim.visc, sim.dt, n, 0, sim.ws,
+                         sim.status)
             self.dts[n:n + 1].copy_(sim.dt)
-        return tape
 
     def forward(self, alpha: float, v0_fluid):
         """v0_fluid: device FP64 [nf, 3] initial fluid velocities (id order).
@@ -132,7 +140,7 @@ class Rollout:
         for n in range(self.K):
             if n % self.C == 0:
                 self.ckpt[n // self.C] = self._snapshot()
-            self._one_step(n, record=False)
+            self._one_step(n)
         return self.fluid_positions()
 
     def fluid_positions(self):
@@ -165,13 +173,16 @@ class Rollout:
         bufs[cur][0][:, :3] = gx[sim.a.id.long()].to(f32)
         alpha_bar = torch.zeros(1, dtype=torch.float64, device=dev)
         nseg = (self.K + self.C - 1) // self.C
+        if len(self.tapes) < min(self.C, self.K):
+            self.tapes = [_Tape(sim) for _ in range(min(self.C, self.K))]
         for s in reversed(range(nseg)):
             n0, n1 = s * self.C, min(self.K, (s + 1) * self.C)
             self._restore(self.ckpt[s])
-            tapes = [self._one_step(k, record=True) for k in range(n0, n1)]
+            for k in range(n0, n1):
+                self._one_step(k, self.tapes[k - n0])
             for k in reversed(range(n0, n1)):
-                t = tapes[k - n0]
-                st = t.state(n, nb)
+                t = self.tapes[k - n0]
+                st = t.state()
                 xb, vb, vpb = bufs[cur]
                 adj = _adjoint_struct(xb, vb, vpb, ace_bar)
                 dt = self.dts if self.fixed_dts is None else self.fixed_dts
@@ -182,7 +193,6 @@ class Rollout:
                 nxt = 1 - cur
                 sph.sph_build_cells_backward(t.perm, n, adj, _adjoint_struct(*bufs[nxt], None))
                 cur = nxt
-            del tapes
         xb, vb, vpb = bufs[cur]
         # the initial state sets v^{-1} = v^0: both adjoints belong to v0
         gv0 = (vb[nb:, :3] + vpb[nb:, :3]).to(torch.float64)
