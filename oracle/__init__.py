@@ -30,7 +30,7 @@ class Params(C.Structure):
                 ("c0", C.c_double), ("alpha", C.c_double), ("eta2", C.c_double),
                 ("g", C.c_double * 3), ("mass", C.c_double), ("cfl", C.c_double),
                 ("kernel", C.c_int32), ("verlet_ns", C.c_int32),
-                ("bound_floor", C.c_int32), ("pad_", C.c_int32)]
+                ("bound_floor", C.c_int32), ("pad_", C.c_int32), ("tensile_dp", C.c_double)]
 
 
 def build(force: bool = True) -> str:
@@ -105,7 +105,8 @@ def params(phys, **override) -> Params:
     """Oracle parameter struct from a layout's physics constants."""
     d = dict(h=phys.h, rho0=phys.rho0, gamma=phys.gamma, c0=phys.c0, alpha=phys.alpha,
              eta2=phys.eta2, g=tuple(phys.g), mass=phys.mass, cfl=phys.cfl, kernel=phys.kernel,
-             verlet_ns=phys.verlet_ns, bound_floor=phys.bound_floor)
+             verlet_ns=phys.verlet_ns, bound_floor=phys.bound_floor,
+             tensile_dp=phys.tensile_dp)
     d.update(override)
     P = Params()
     for k, v in d.items():

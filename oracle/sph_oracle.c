@@ -18,6 +18,8 @@
  *     paper defers the equations to its ref. [11]; the standard forms of the
  *     cited schemes are used and every reading is listed in the design notes.
  *   - Kernel: Wendland quintic (default) or the paper's cubic spline.
+ *   - Optional tensile correction (the per-particle "tensil" of Table 3,
+ *     following the paper's ref. [34]); off unless tensile_dp > 0.
  *
  * Summation order: the neighbours of a target are summed in ascending id
  * order, so the O(N^2) brute-force search and the cell-list search give
@@ -48,6 +50,7 @@ typedef struct {
     int32_t verlet_ns; /* a corrective Verlet step every verlet_ns steps        */
     int32_t bound_floor; /* 1: boundary density never falls below rho0          */
     int32_t pad_;
+    double tensile_dp;   /* tensile correction: spacing dp of f = W(r)/W(dp); 0 off */
 } ora_params;
 
 /* ------------------------------------------------------------------------ */
@@ -221,10 +224,34 @@ static int nbr_cells(int a, int nb, const uint8_t *excl, const double *x, double
 }
 
 /* ------------------------------------------------------------------------ */
+/* Tensile correction (Table 3 "tensil", following the paper's ref. [34]):
+ * per particle R_a = 0.01 P_a/rho_a^2 if P_a > 0, else 0.2 |P_a|/rho_a^2;
+ * a pair adds T_ab = (R_a + R_b) f_ab^4, f_ab = W(r_ab)/W(dp), to the pressure
+ * factor of the momentum equation.  Pinned by: the closed-form ratios at
+ * r = dp (f = 1) and at W(r) = W(dp)/2 (f^4 = 1/16) for both pressure signs,
+ * momentum conservation with negative pressures, and the VJP finite
+ * differences with the correction on.                                       */
+static double tens_r(double p_over_rho2)
+{
+    return p_over_rho2 > 0.0 ? 0.01 * p_over_rho2 : -0.2 * p_over_rho2;
+}
+
+/* dR/d(P/rho^2) on the side of the sign of P/rho^2 */
+static double tens_eps(double p_over_rho2) { return p_over_rho2 > 0.0 ? 0.01 : -0.2; }
+
+/* f^4 = (W(r)/W(dp))^4 */
+static double tens_f4(const ora_params *p, double r)
+{
+    const double f = ora_w(p, r) / ora_w(p, p->tensile_dp);
+    return (f * f) * (f * f);
+}
+
+/* ------------------------------------------------------------------------ */
 /* Particle interaction for one target (Section 2 stage PI; Table 1 terms).
  *   grad_a W_ab      = F_ab r_ab,  r_ab = x_a - x_b
  *   continuity       drho_a/dt = sum_b m (v_a - v_b).r_ab F_ab           (any a)
- *   momentum         dv_a/dt   = g - sum_b m (P_a/rho_a^2 + P_b/rho_b^2 + Pi_ab) F_ab r_ab
+ *   momentum         dv_a/dt   = g - sum_b m (P_a/rho_a^2 + P_b/rho_b^2 + Pi_ab
+ *                                              [+ T_ab]) F_ab r_ab
  *   Monaghan viscosity: mu_ab = h v_ab.r_ab / (r^2 + eta2);
  *                    Pi_ab = -alpha cbar mu_ab / rhobar if v_ab.r_ab < 0, else 0
  *   visc_a           = max_b |mu_ab|   (fluid targets; used by the time step)
@@ -261,7 +288,9 @@ static void pair_sum(const ora_params *p, int a, int nb, const int *nbr, int cnt
         if (fabs(mu) > vmax) vmax = fabs(mu);
         double Pi = 0.0;
         if (vdr < 0.0) Pi = -p->alpha * (0.5 * (ca + cb)) * mu / (0.5 * (ra + rb));
-        const double coef = m * (pa + pb + Pi) * F;
+        double T = 0.0;
+        if (p->tensile_dp > 0.0) T = (tens_r(pa) + tens_r(pb)) * tens_f4(p, sqrt(r2));
+        const double coef = m * (pa + pb + Pi + T) * F;
         sx -= coef * rx;
         sy -= coef * ry;
         sz -= coef * rz;
@@ -632,16 +661,29 @@ ORA_EXPORT void ora_interact_vjp(int n, int nb, const double *x, const double *v
                     dPi_drb = -p->alpha * mu * (0.5 * dcb / rbar - 0.5 * cbar / (rbar * rbar));
                     dPi_dal = -cbar * mu / rbar;
                 }
-                const double s = pa + pb + Pi;
+                /* tensile term: T = (R_a + R_b) f^4, dT/dx_a = (R_a + R_b) 4 f^3 f' r/|r|,
+                 * f' = (dW/dr)/W(dp) = F |r| / W(dp); dT/drho = eps d(P/rho^2)/drho f^4 */
+                double T = 0.0, dT_dr = 0.0, dT_dra = 0.0, dT_drb = 0.0;
+                if (p->tensile_dp > 0.0) {
+                    const double wdp = ora_w(p, p->tensile_dp);
+                    const double f = ora_w(p, rr) / wdp;
+                    const double Rab = tens_r(pa) + tens_r(pb);
+                    T = Rab * f * f * f * f;
+                    dT_dr = Rab * 4.0 * f * f * f * F / wdp; /* times r[d] */
+                    dT_dra = tens_eps(pa) * dpa * f * f * f * f;
+                    dT_drb = tens_eps(pb) * dpb * f * f * f * f;
+                }
+                const double s = pa + pb + Pi + T;
                 const double Q = Ab[0] * r[0] + Ab[1] * r[1] + Ab[2] * r[2];
                 for (int d = 0; d < 3; ++d) {
                     const double dmu_dr = h * vv[d] / den - 2.0 * mu * r[d] / den;
                     const double dmu_dv = h * r[d] / den;
-                    gx[d] += -m * (F * Q * dPi_dmu * dmu_dr + s * Q * Fr * r[d] + s * F * Ab[d]);
+                    gx[d] += -m * (F * Q * (dPi_dmu * dmu_dr + dT_dr * r[d]) + s * Q * Fr * r[d] +
+                                   s * F * Ab[d]);
                     gv[d] += -m * F * Q * dPi_dmu * dmu_dv;
                 }
-                gra = -m * F * Q * (dpa + dPi_dra);
-                grb = -m * F * Q * (dpb + dPi_drb);
+                gra = -m * F * Q * (dpa + dPi_dra + dT_dra);
+                grb = -m * F * Q * (dpb + dPi_drb + dT_drb);
                 ab += -m * F * Q * dPi_dal;
             }
             for (int d = 0; d < 3; ++d) {

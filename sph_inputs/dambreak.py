@@ -36,6 +36,8 @@ class Physics:
 
     ``h`` is the smoothing length; the kernel support is ``2h``.
     ``kernel`` 0 = Wendland quintic, 1 = cubic spline.
+    ``tensile_dp`` > 0 switches the tensile correction on, with that spacing
+    in f = W(r)/W(dp); 0 = off.
     """
 
     dp: float
@@ -51,6 +53,7 @@ class Physics:
     verlet_ns: int = 40
     bound_floor: int = 1
     kernel: int = 0
+    tensile_dp: float = 0.0
 
 
 def physics(dp: float, column_height: float = 0.2, alpha: float = 0.1,
