@@ -53,7 +53,7 @@
 extern "C" {
 #endif
 
-#define SPH_ABI_VERSION 2 /* 2: npairs of sph_interact has two entries */
+#define SPH_ABI_VERSION 3 /* 2: two-entry npairs; 3: sph_params.tensile_dp */
 #define SPH_API __attribute__((visibility("default")))
 #define SPH_EXCLUDED INT32_MAX /* cell index of a particle outside the domain */
 
@@ -106,6 +106,11 @@ typedef struct {
     int32_t verlet_ns;   /* corrective Verlet step every verlet_ns steps (>= 1)  */
     int32_t bound_floor; /* 1: boundary density floored at rho0 after each step  */
     int32_t pad_;
+    double tensile_dp;   /* tensile correction (Table 3 "tensil", ref. [34]): 0 = off;
+                          * > 0: the particle spacing dp, 0 < dp < 2h.  A pair then
+                          * adds (R_a + R_b) f^4, f = W(r)/W(dp), to the pressure
+                          * factor of the momentum equation, with R = 0.01 P/rho^2
+                          * for P > 0 and 0.2 |P|/rho^2 for P < 0.                 */
 } sph_params;
 
 /* Particle state (structure of arrays); one instance per side of a double

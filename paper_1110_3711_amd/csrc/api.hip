@@ -32,6 +32,8 @@ bool params_ok(const sph_grid *g, const sph_params *p)
     if (p->kernel != SPH_WENDLAND5 && p->kernel != SPH_CUBIC_SPLINE) return false;
     if (p->verlet_ns < 1) return false;
     if (!(p->eta2 > 0.0) || !(p->alpha >= 0.0) || !(p->cfl > 0.0)) return false;
+    // tensile correction: off (0) or a spacing inside the support
+    if (!(p->tensile_dp >= 0.0) || !(p->tensile_dp < 2.0 * p->h)) return false;
     // the (2 nsub + 1)^3 stencil must cover the support 2h, with margin for
     // FP32 rounding of the offsets
     if (g->nsub * g->cell < 2.0 * p->h * (1.0 + ldexp(1.0, -21))) return false;

@@ -315,7 +315,7 @@ struct LaneCtx {
 
 // One work item: the targets of cell `key` (of the list kind KIND) against
 // its stencil, staged tile by tile through the workgroup's LDS.
-template <int KIND, bool STATS, int KER, class L>
+template <int KIND, bool STATS, int KER, bool TENS, class L>
 __device__ __forceinline__ void pair_item(const PairConsts &K, const PairArgs &A, L &S,
                                           const LaneCtx &C, int32_t key,
                                           unsigned long long &pairs_acc)
@@ -498,6 +498,11 @@ __device__ __forceinline__ void pair_item(const PairConsts &K, const PairArgs &A
                 const float ca = K.c0 * ta2 * ta;
                 dpa = (ca * inv_ra) * (ca * inv_ra) - 2.f * pa.w * inv_ra;
             }
+            // tensile correction: R_a = eps_a P_a/rho_a^2, eps = 0.01 (P > 0) or
+            // -0.2 (P < 0); backward: dR_a/drho_a = eps_a d(P/rho^2)/drho
+            const float eps_a = pa.w > 0.f ? 0.01f : -0.2f;
+            const float ra_t = TENS ? eps_a * pa.w : 0.f;
+            const float eda = TENS ? eps_a * dpa : 0.f;
             // accumulators: forward (s0..s3 = sums for a.xyz and drho in units of
             // gs, vmf = max |u|); backward (s0..s2 = xbar, s3 = rhobar, s4..s6 = vbar,
             // s7 = alphabar)
@@ -526,6 +531,24 @@ __device__ __forceinline__ void pair_item(const PairConsts &K, const PairArgs &A
                     G = qq < 1.f ? __builtin_fmaf(2.25f, qq, -3.f)
                                  : K.kco * (t * t) * __builtin_amdgcn_rcpf(r);
                 }
+                // tensile correction: f = Wn(r) / Wn(dp), R_ab = R_a + R_b
+                float f4 = 0.f, f3 = 0.f, rab = 0.f;
+                if (TENS && (FLUID || BWD)) {
+                    float wn;
+                    if (KER == SPH_WENDLAND5) {
+                        const float wq2 = wq * wq;
+                        wn = (wq2 * wq2) * __builtin_fmaf(2.f * K.inv_h, r, 1.f);
+                    } else {
+                        const float t = 2.f - qq;
+                        wn = qq < 1.f ? __builtin_fmaf(qq * qq, __builtin_fmaf(0.75f, qq, -1.5f), 1.f)
+                                      : 0.25f * (t * t) * t;
+                    }
+                    const float f = wn * K.inv_wndp;
+                    const float f2 = f * f;
+                    f3 = f2 * f;
+                    f4 = f2 * f2;
+                    rab = __builtin_fmaf(pb.w, pb.w > 0.f ? 0.01f : -0.2f, ra_t);
+                }
                 const float vx = va.x - vb.x, vy = va.y - vb.y, vz = va.z - vb.z;
                 const float vdr = __builtin_fmaf(vz, rz, __builtin_fmaf(vy, ry, vx * rx));
                 if (!BWD) {
@@ -535,8 +558,9 @@ __device__ __forceinline__ void pair_item(const PairConsts &K, const PairArgs &A
                         vmf = fmaxf(vmf, fabsf(u));
                         const float tb = __builtin_fmaf(vb.w, K.inv_rho0, 1.0f);
                         const float crk = __builtin_fmaf(tb, __builtin_fmaf(tb, K.kh, kta), kta2);
-                        // P_a/rho_a^2 + P_b/rho_b^2 + Pi_ab
-                        const float sm = __builtin_fmaf(crk, fminf(u, 0.f), pa.w + pb.w);
+                        // P_a/rho_a^2 + P_b/rho_b^2 + Pi_ab [+ R_ab f^4]
+                        float sm = __builtin_fmaf(crk, fminf(u, 0.f), pa.w + pb.w);
+                        if (TENS) sm = __builtin_fmaf(rab, f4, sm);
                         const float coef = sm * G;
                         s0 = __builtin_fmaf(coef, rx, s0);
                         s1 = __builtin_fmaf(coef, ry, s1);
@@ -547,7 +571,7 @@ __device__ __forceinline__ void pair_item(const PairConsts &K, const PairArgs &A
                     const float F = K.gs * G;
                     // Pair contribution to the loss, symmetric in (a, b):
                     //   (abar_a - abar_b) . T_ab + (Dbar_a + Dbar_b) S_ab,
-                    //   T_ab = -m s F r_ab, s = P_a/rho_a^2 + P_b/rho_b^2 + Pi_ab,
+                    //   T_ab = -m s F r_ab, s = P_a/rho_a^2 + P_b/rho_b^2 + Pi_ab [+ R_ab f^4],
                     //   S_ab = m (v_ab . r_ab) F;  its derivatives w.r.t. the gatherer a.
                     const float4 ab = lds_load4(sAb + off);
                     const float dax = aa.x - ab.x, day = aa.y - ab.y, daz = aa.z - ab.z;
@@ -559,7 +583,10 @@ __device__ __forceinline__ void pair_item(const PairConsts &K, const PairArgs &A
                     const float mneg = fminf(mu, 0.f);
                     // d/drho_a of s: d(P/rho^2)/drho + dPi/drho_a
                     const float dpi_dra = K.kpi * K.inv_rho0 * __builtin_fmaf(2.f, ta, -tb) * mneg;
-                    s3 = __builtin_fmaf(-F * Q, dpa + dpi_dra, s3);
+                    // (+ the tensile term's dR_a/drho_a f^4)
+                    float drs = dpa + dpi_dra;
+                    if (TENS) drs = __builtin_fmaf(eda, f4, drs);
+                    s3 = __builtin_fmaf(-F * Q, drs, s3);
                     if (FLUID) {
                         // (dF/dr) / r; 0 for the self pair
                         float Fr;
@@ -576,11 +603,14 @@ __device__ __forceinline__ void pair_item(const PairConsts &K, const PairArgs &A
                         const float c1 = sD * F, c2 = sD * vdr * Fr;
                         // momentum
                         const float pi = K.kpi * cr * mneg;
-                        const float sm = pa.w + pb.w + pi;
+                        float sm = pa.w + pb.w + pi;
+                        if (TENS) sm = __builtin_fmaf(rab, f4, sm);
                         const float dpi_dmu = mu < 0.f ? K.kpi * cr : 0.f;
                         const float e1 = F * Q * dpi_dmu;
                         const float e1h = e1 * K.h * invden;
-                        const float e2 = __builtin_fmaf(-2.f * e1 * invden, mu, sm * Q * Fr);
+                        float e2 = __builtin_fmaf(-2.f * e1 * invden, mu, sm * Q * Fr);
+                        // tensile: d(R_ab f^4)/dx_a = R_ab 4 f^3 (F / W(dp)) r_ab
+                        if (TENS) e2 = __builtin_fmaf(4.f * rab * f3 * K.inv_wdp, F * F * Q, e2);
                         const float e3 = sm * F;
                         s0 += __builtin_fmaf(c1, vx, c2 * rx) - __builtin_fmaf(e1h, vx, __builtin_fmaf(e2, rx, e3 * dax));
                         s1 += __builtin_fmaf(c1, vy, c2 * ry) - __builtin_fmaf(e1h, vy, __builtin_fmaf(e2, ry, e3 * day));
@@ -714,7 +744,7 @@ __device__ __forceinline__ void pair_item(const PairConsts &K, const PairArgs &A
     }
 }
 
-template <int KIND, bool STATS, int KER>
+template <int KIND, bool STATS, int KER, bool TENS>
 __global__ __launch_bounds__(kThreads) void k_interact(PairConsts K, PairArgs A)
 {
     using T = KindTraits<KIND>;
@@ -807,11 +837,11 @@ __global__ __launch_bounds__(kThreads) void k_interact(PairConsts K, PairArgs A)
         if (!T::fused || kind == 0) {
             const int32_t key = __builtin_amdgcn_readfirstlane(
                 min(max(A.items[ibase + item], 0), 2 * K.ncell - 1));
-            pair_item<T::first, STATS, KER>(K, A, S, C, key, p1);
+            pair_item<T::first, STATS, KER, TENS>(K, A, S, C, key, p1);
         } else {
             const int32_t key =
                 __builtin_amdgcn_readfirstlane(min(max(A.items2[item], 0), 2 * K.ncell - 1));
-            pair_item<T::second, STATS, KER>(K, A, S, C, key, p2);
+            pair_item<T::second, STATS, KER, TENS>(K, A, S, C, key, p2);
         }
     }
     if (A.npairs && C.lane == 0) {
@@ -901,6 +931,24 @@ static PairConsts pair_consts(const sph_grid *g, const sph_params *p, int32_t n)
         K.kco = 0.f;
     }
     K.mgs = (float)(p->mass * (double)K.gs);
+    // tensile correction: kernel shape Wn = W / aD at the particle spacing
+    K.tensile = p->tensile_dp > 0.0 ? 1 : 0;
+    K.inv_wndp = 0.f;
+    K.inv_wdp = 0.f;
+    if (K.tensile) {
+        const double q = p->tensile_dp / h;
+        double wn, adk;
+        if (p->kernel == SPH_CUBIC_SPLINE) {
+            wn = q < 1.0 ? 1.0 - 1.5 * q * q + 0.75 * q * q * q : 0.25 * (2.0 - q) * (2.0 - q) * (2.0 - q);
+            adk = ac;
+        } else {
+            const double t = 1.0 - 0.5 * q;
+            wn = t * t * t * t * (2.0 * q + 1.0);
+            adk = ad;
+        }
+        K.inv_wndp = (float)(1.0 / wn);
+        K.inv_wdp = (float)(1.0 / (adk * wn));
+    }
     K.c0 = (float)p->c0;
     K.rho0 = (float)p->rho0;
     K.inv_rho0 = (float)(1.0 / p->rho0);
@@ -921,7 +969,7 @@ static PairConsts pair_consts(const sph_grid *g, const sph_params *p, int32_t n)
     return K;
 }
 
-template <int KIND, bool STATS, int KER>
+template <int KIND, bool STATS, int KER, bool TENS>
 static hipError_t launch_one(const PairConsts &K, const PairArgs &A, hipStream_t s)
 {
     int dev = 0, cus = 0, occ = 0;
@@ -929,11 +977,11 @@ static hipError_t launch_one(const PairConsts &K, const PairArgs &A, hipStream_t
     if (e != hipSuccess) return e;
     e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     if (e != hipSuccess) return e;
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_interact<KIND, STATS, KER>, kThreads, 0);
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_interact<KIND, STATS, KER, TENS>, kThreads, 0);
     if (e != hipSuccess) return e;
     if (cus <= 0) cus = 1;
     if (occ <= 0) occ = 1;
-    k_interact<KIND, STATS, KER><<<cus * occ, kThreads, 0, s>>>(K, A);
+    k_interact<KIND, STATS, KER, TENS><<<cus * occ, kThreads, 0, s>>>(K, A);
     return hipGetLastError();
 }
 
@@ -942,12 +990,19 @@ template <int KIND>
 static hipError_t launch_kind(const PairConsts &K, const PairArgs &A, bool stats, hipStream_t s)
 {
     constexpr bool fwd = KIND == kFwdFluid || KIND == kFwdBound || KIND == kFwdAll;
+    const bool st = fwd && stats;
     if (K.kernel == SPH_CUBIC_SPLINE) {
-        if (fwd && stats) return launch_one<KIND, fwd, SPH_CUBIC_SPLINE>(K, A, s);
-        return launch_one<KIND, false, SPH_CUBIC_SPLINE>(K, A, s);
+        if (K.tensile)
+            return st ? launch_one<KIND, fwd, SPH_CUBIC_SPLINE, true>(K, A, s)
+                      : launch_one<KIND, false, SPH_CUBIC_SPLINE, true>(K, A, s);
+        return st ? launch_one<KIND, fwd, SPH_CUBIC_SPLINE, false>(K, A, s)
+                  : launch_one<KIND, false, SPH_CUBIC_SPLINE, false>(K, A, s);
     }
-    if (fwd && stats) return launch_one<KIND, fwd, SPH_WENDLAND5>(K, A, s);
-    return launch_one<KIND, false, SPH_WENDLAND5>(K, A, s);
+    if (K.tensile)
+        return st ? launch_one<KIND, fwd, SPH_WENDLAND5, true>(K, A, s)
+                  : launch_one<KIND, false, SPH_WENDLAND5, true>(K, A, s);
+    return st ? launch_one<KIND, fwd, SPH_WENDLAND5, false>(K, A, s)
+              : launch_one<KIND, false, SPH_WENDLAND5, false>(K, A, s);
 }
 
 static PairArgs base_args(const sph_state *st, const sph_cells *cells)

@@ -112,6 +112,11 @@ struct PairConsts {
     float kco;       // cubic: kc_out / kc_in = -3h/4
     float mgs;       // mass * gs
     float kh;        // -alpha h c0 / rho0: Pi_ab = kh cr min(u, 0), mu = h u
+    // tensile correction (tensile != 0): f = Wn(r) / Wn(dp) with the kernel
+    // shape Wn = W / aD; inv_wdp = 1 / W(dp) with aD (for dT/dr = R 4 f^3 F / W(dp))
+    int32_t tensile;
+    float inv_wndp;  // 1 / Wn(dp)
+    float inv_wdp;   // 1 / W(dp)
     float c0;
     float rho0;
     float inv_rho0;

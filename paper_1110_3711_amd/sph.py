@@ -21,7 +21,7 @@ SPH_DEV_OUT_OF_GRID, SPH_DEV_NONFINITE = 1, 2
 SPH_FIXED_DT, SPH_ADJOINT = 1, 2
 SPH_PI_FLUID, SPH_PI_BOUNDARY, SPH_PI_ALL = 1, 2, 3
 SPH_EXCLUDED = 2**31 - 1
-ABI_VERSION = 2
+ABI_VERSION = 3
 
 EXPORTS = ["sph_workspace_bytes", "sph_abi_version", "sph_encode", "sph_decode",
            "sph_build_cells", "sph_interact", "sph_step", "sph_interact_backward",
@@ -38,7 +38,7 @@ class Params(C.Structure):
                 ("c0", C.c_double), ("alpha", C.c_double), ("eta2", C.c_double),
                 ("g", C.c_double * 3), ("mass", C.c_double), ("cfl", C.c_double),
                 ("kernel", C.c_int32), ("verlet_ns", C.c_int32), ("bound_floor", C.c_int32),
-                ("pad_", C.c_int32)]
+                ("pad_", C.c_int32), ("tensile_dp", C.c_double)]
 
 
 class State(C.Structure):
@@ -187,6 +187,7 @@ def make_params(phys) -> Params:
     for d in range(3):
         p.g[d] = phys.g[d]
     p.kernel, p.verlet_ns, p.bound_floor = phys.kernel, phys.verlet_ns, phys.bound_floor
+    p.tensile_dp = phys.tensile_dp
     return p
 
 

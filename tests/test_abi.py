@@ -37,7 +37,7 @@ def test_library_exports_every_declared_symbol(lib):
     for name in _declared():
         assert hasattr(lib, name), name
     assert sorted(sph.EXPORTS) == _declared()
-    assert lib.sph_abi_version() == 2
+    assert lib.sph_abi_version() == 3
 
 
 def _grid():
@@ -97,6 +97,11 @@ def test_validation_errors_before_any_device_work(lib):
     p3.gamma = 5.0
     assert lib.sph_interact(C.byref(g), C.byref(p3), C.byref(st), C.byref(cells), 3, fake, fake,
                             None, None, fake, 1 << 40, None) == sph.SPH_ERR_ARG
+    p5 = sph.make_params(physics(0.01))
+    for bad in (-0.01, 2.0 * p5.h, float("nan")):  # tensile spacing outside [0, 2h)
+        p5.tensile_dp = bad
+        assert lib.sph_interact(C.byref(g), C.byref(p5), C.byref(st), C.byref(cells), 3, fake,
+                                fake, None, None, fake, 1 << 40, None) == sph.SPH_ERR_ARG
     p4 = sph.make_params(physics(0.01))
     p4.kernel = 2  # only SPH_WENDLAND5 (0) and SPH_CUBIC_SPLINE (1) exist
     assert lib.sph_step(C.byref(g), C.byref(p4), C.byref(st), fake, fake, fake, 0, 0, None, fake,
