@@ -106,6 +106,26 @@ def _ptr(t):
     return None if t is None else C.c_void_p(t.data_ptr())
 
 
+def _need(t, dtype, count, name, optional=False):
+    """A device array passed to the C ABI must be a contiguous CUDA tensor of
+    the expected dtype with at least `count` elements (the library cannot
+    check device buffer sizes itself)."""
+    import torch
+
+    if t is None:
+        if optional:
+            return
+        raise SphError(f"{name}: a device array is required")
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
+        raise SphError(f"{name}: expected a CUDA tensor")
+    if t.dtype != dtype:
+        raise SphError(f"{name}: expected {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise SphError(f"{name}: expected a contiguous tensor")
+    if t.numel() < count:
+        raise SphError(f"{name}: {t.numel()} elements, need at least {count}")
+
+
 def _stream(stream=None):
     import torch
 
@@ -121,16 +141,34 @@ def sph_workspace_bytes(grid: Grid, n: int) -> int:
 
 
 def sph_encode(grid, params, x, v, rho, state, dev_status, stream=None):
+    import torch
+
+    n = state.n
+    _need(x, torch.float64, 3 * n, "x")
+    _need(v, torch.float64, 3 * n, "v")
+    _need(rho, torch.float64, n, "rho")
+    _need(dev_status, torch.int32, 1, "dev_status")
     _check(load().sph_encode(C.byref(grid), C.byref(params), _ptr(x), _ptr(v), _ptr(rho),
                              C.byref(state), _ptr(dev_status), _stream(stream)), "sph_encode")
 
 
 def sph_decode(grid, params, state, x, v, rho, stream=None):
+    import torch
+
+    n = state.n
+    _need(x, torch.float64, 3 * n, "x")
+    _need(v, torch.float64, 3 * n, "v")
+    _need(rho, torch.float64, n, "rho")
     _check(load().sph_decode(C.byref(grid), C.byref(params), C.byref(state), _ptr(x), _ptr(v),
                              _ptr(rho), _stream(stream)), "sph_decode")
 
 
 def sph_build_cells(grid, src, dst, cells, perm, ws, dev_status, stream=None):
+    import torch
+
+    _need(perm, torch.int32, src.n, "perm")
+    _need(ws, torch.uint8, 1, "ws")
+    _need(dev_status, torch.int32, 1, "dev_status")
     _check(load().sph_build_cells(C.byref(grid), C.byref(src), C.byref(dst), C.byref(cells),
                                   _ptr(perm), _ptr(ws), ws.numel(), _ptr(dev_status),
                                   _stream(stream)), "sph_build_cells")
@@ -138,8 +176,14 @@ def sph_build_cells(grid, src, dst, cells, perm, ws, dev_status, stream=None):
 
 def sph_interact(grid, params, state, cells, ace, visc, npairs, ws, nbr_stats=None,
                  parts=SPH_PI_ALL, stream=None):
-    if npairs is not None and npairs.numel() < 2:
-        raise SphError("npairs needs 2 entries (fluid-target, boundary-target pairs)")
+    import torch
+
+    n = state.n
+    _need(ace, torch.float32, 4 * n, "ace")
+    _need(visc, torch.float32, n, "visc")
+    _need(npairs, torch.int64, 2, "npairs (fluid-target, boundary-target pairs)", optional=True)
+    _need(nbr_stats, torch.int32, 2 * n, "nbr_stats", optional=True)
+    _need(ws, torch.uint8, 1, "ws")
     _check(load().sph_interact(C.byref(grid), C.byref(params), C.byref(state), C.byref(cells),
                                int(parts), _ptr(ace), _ptr(visc), _ptr(npairs), _ptr(nbr_stats),
                                _ptr(ws), ws.numel(), _stream(stream)), "sph_interact")
@@ -147,6 +191,14 @@ def sph_interact(grid, params, state, cells, ace, visc, npairs, ws, nbr_stats=No
 
 def sph_step(grid, params, state, ace, visc, dt, step, flags, ws, dev_status, adj=None,
              stream=None):
+    import torch
+
+    n = state.n
+    _need(ace, torch.float32, 4 * n, "ace")
+    _need(visc, torch.float32, n, "visc")
+    _need(dt, torch.float64, 1, "dt")
+    _need(ws, torch.uint8, 1, "ws")
+    _need(dev_status, torch.int32, 1, "dev_status")
     _check(load().sph_step(C.byref(grid), C.byref(params), C.byref(state), _ptr(ace), _ptr(visc),
                            _ptr(dt), int(step), int(flags), C.byref(adj) if adj else None,
                            _ptr(ws), ws.numel(), _ptr(dev_status), _stream(stream)), "sph_step")
@@ -154,6 +206,14 @@ def sph_step(grid, params, state, ace, visc, dt, step, flags, ws, dev_status, ad
 
 def sph_interact_backward(grid, params, state, cells, ace_bar, pos_bar, velrho_bar, alpha_bar,
                           ws, stream=None):
+    import torch
+
+    n = state.n
+    _need(ace_bar, torch.float32, 4 * n, "ace_bar")
+    _need(pos_bar, torch.float32, 4 * n, "pos_bar")
+    _need(velrho_bar, torch.float32, 4 * n, "velrho_bar")
+    _need(alpha_bar, torch.float64, 1, "alpha_bar")
+    _need(ws, torch.uint8, 1, "ws")
     _check(load().sph_interact_backward(C.byref(grid), C.byref(params), C.byref(state),
                                         C.byref(cells), _ptr(ace_bar), _ptr(pos_bar),
                                         _ptr(velrho_bar), _ptr(alpha_bar), _ptr(ws), ws.numel(),
@@ -161,6 +221,9 @@ def sph_interact_backward(grid, params, state, cells, ace_bar, pos_bar, velrho_b
 
 
 def sph_build_cells_backward(perm, n, dst_bar, src_bar, stream=None):
+    import torch
+
+    _need(perm, torch.int32, n, "perm")
     _check(load().sph_build_cells_backward(_ptr(perm), int(n), C.byref(dst_bar),
                                            C.byref(src_bar), _stream(stream)),
            "sph_build_cells_backward")
