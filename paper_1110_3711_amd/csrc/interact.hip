@@ -1,26 +1,39 @@
 // interact.hip -- particle-interaction stage (Section 2 "PI"): fluid targets
-// (F-F and F-B fused in one kernel, Section 4.5) and boundary targets (B-F).
+// (F-F and F-B fused, Section 4.5) and boundary targets (B-F), and the
+// vector-Jacobian product of the same pair terms.
 //
 // Work decomposition (gfx950, wave64):
-//   * one workgroup per non-empty target cell, taken from a device work queue
-//     (dynamic scheduling, like the OpenMP dynamic scheduler of Section 3.4);
+//   * one workgroup per non-empty target cell, taken from device work queues
+//     (dynamic scheduling, like the OpenMP dynamic scheduler of Section 3.4):
+//     the fluid cell list is cut into one chunk per XCD, so that cells with
+//     common stencil neighbours run on the XCD that caches them; a full stage
+//     is one launch in which the boundary cells with fluid in reach are
+//     interleaved with the fluid cells;
 //   * the (2n+1)^2 X-runs of the stencil (Section 4.4: three consecutive
 //     cells along X are one contiguous range of the sorted arrays) are staged
 //     into LDS in the frame of the target cell: each candidate's offset gets
-//     (k_b - k_a) * cell added once, in FP32 (exact for |k_b - k_a| <= 2);
+//     (k_b - k_a) * cell added once, in FP32 (exact for |k_b - k_a| <= 2),
+//     and the staged candidates are ordered by 32 bins of their x, so that a
+//     target scans only the window of bins within 2h of its own x;
 //   * one wavefront per target: 64 candidates per step are tested for
 //     r^2 < (2h)^2, survivors are compacted with a ballot into a per-wave ring
 //     in LDS, and every full batch of 64 survivors is evaluated with all lanes
 //     busy.  This removes the divergence of a thread-per-target loop (the
 //     "code divergence" problem of Section 4) without any neighbour list in
 //     HBM;
-//   * per-lane partial sums are reduced across the wave (DPP) once per target
-//     and written once (Section 4.5: accumulate in registers, write at the end).
+//   * per-lane partial sums are reduced across the wave once per target (DPP
+//     butterflies) and written once (Section 4.5: accumulate in registers,
+//     write at the end).  No float atomics: results are bitwise reproducible.
 //
 // The target itself is one of its staged candidates: it passes the distance
 // test with r = 0 and contributes exactly zero to every sum (r_ab = 0,
 // v_ab = 0, mu = 0), so it is not filtered per candidate; it is only removed
 // from the pair count.
+//
+// Template parameters of the kernels: the work-list kind (fluid, boundary,
+// or both in one launch; forward or adjoint), per-pair diagnostics (STATS),
+// the kernel shape (KER: Wendland quintic or cubic spline) and the tensile
+// correction (TENS).
 #include "sph_internal.h"
 
 namespace sph {
