@@ -214,8 +214,9 @@ SPH_API sph_status sph_interact(const sph_grid *g, const sph_params *p, const sp
  * the position update is FP64 and re-bins (cell, offset).  Boundary slots
  * keep position and velocity; their density follows the same rule and is
  * floored at rho0 if bound_floor.  Unless SPH_FIXED_DT, a non-finite value
- * in ace or visc (any slot) or a non-finite time step sets SPH_DEV_NONFINITE,
- * writes NaN to dt[0] and leaves the state unchanged.
+ * in ace or visc (any slot) or a non-finite time step (also: no fluid slot,
+ * hence no limit on dt) sets SPH_DEV_NONFINITE, writes NaN to dt[0] and
+ * leaves the state unchanged.
  * Adjoint mode (flags SPH_ADJOINT, adj != NULL): st, ace and dt[0] are the
  * state, (a, D) and time step of the forward step being transposed (st before
  * its update).  In: adj->pos_bar, velrho_bar, velrho_prev_bar = adjoints of

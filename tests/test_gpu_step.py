@@ -187,3 +187,48 @@ def test_boundaries_fixed_and_floored(ora):
     assert np.array_equal(x[: lay.nb], xq[: lay.nb])
     assert np.all(v[: lay.nb] == 0)
     assert np.all(r[: lay.nb] >= lay.phys.rho0) and np.any(r[: lay.nb] > lay.phys.rho0)
+
+
+def test_degenerate_layouts(ora):
+    """No particles: every stage is a no-op.  Boundary particles only: no
+    fluid in reach, so every output is zero; there is no fluid particle to
+    set a time step (the oracle's is infinite), so the CFL step flags
+    SPH_DEV_NONFINITE and keeps the state; with a fixed time step the
+    boundary densities do not change (D = 0)."""
+    import torch
+
+    from paper_1110_3711_amd import sph
+
+    lay = dam_break(0.02, 11103711 + 12, fluid=(0.06, 0.06, 0.06), tank=(0.12, 0.1, 0.1))
+    empty = lay.copy()
+    empty.x, empty.v, empty.rho, empty.nb = lay.x[:0], lay.v[:0], lay.rho[:0], 0
+    print("degenerate: n = 0", flush=True)
+    sim = sph.Simulation(empty, nsub=1)
+    sim.step()
+    torch.cuda.synchronize()
+    assert sim.dev_status() & sph.SPH_DEV_NONFINITE  # no fluid: no time step
+    bnd = lay.copy()
+    bnd.x, bnd.v, bnd.rho = lay.x[: lay.nb], lay.v[: lay.nb], lay.rho[: lay.nb]
+    print(f"degenerate: boundary only n={bnd.n}", flush=True)
+    sim = sph.Simulation(bnd, nsub=1)
+    sim.build_cells()
+    sim.npairs.zero_()
+    sim.ace.fill_(5.0)
+    sim.visc.fill_(5.0)
+    sim.interact()
+    torch.cuda.synchronize()
+    assert torch.all(sim.ace[: bnd.n] == 0) and torch.all(sim.visc[: bnd.n] == 0)
+    assert int(sim.npairs.sum()) == 0
+    P = ora.params(bnd.phys)
+    excl = np.zeros(bnd.n, dtype=np.uint8)
+    ace, visc, _, _ = ora.interact(bnd.x, bnd.v, bnd.rho, bnd.nb, P, excl=excl)
+    assert np.isinf(ora.time_step(bnd.rho, ace, visc, bnd.nb, P, excl))
+    before = sim.a.velrho.clone()
+    sim.update()
+    torch.cuda.synchronize()
+    assert sim.dev_status() & sph.SPH_DEV_NONFINITE
+    assert torch.isnan(sim.dt).all() and torch.equal(before, sim.a.velrho)
+    sim.status.zero_()
+    sim.update(fixed_dt=1e-4)
+    torch.cuda.synchronize()
+    assert sim.dev_status() == 0 and torch.equal(before[:, 3], sim.a.velrho[:, 3])
