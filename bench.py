@@ -17,6 +17,7 @@ oracle on the host cores on a bounded sample of the same workload.
 from __future__ import annotations
 
 import argparse
+import dataclasses
 import hashlib
 import json
 import os
@@ -35,6 +36,11 @@ METRIC = "pair interactions/s + steps/s, 1M-particle dam break FP32; adjoint/for
 # Tait pressure terms, momentum accumulation); see the design notes.
 FLOP_FLUID_PAIR = 49
 FLOP_BOUND_PAIR = 24
+# the cubic spline's gradient factor costs one operation more than the
+# Wendland one; the tensile correction adds 13 per fluid-target pair (kernel
+# shape 6, f^4 2, R_b 2, R_ab 1, accumulate 2)
+FLOP_CUBIC_EXTRA = 1
+FLOP_TENSILE_EXTRA = 13
 PEAK_FP32_VECTOR = 157.3e12   # MI355X FP32 vector peak (FLOP/s)
 PAPER_CONTEXT = "GTX 480: 10.1 steps/s at 1,011,354 particles (paper Table 4; other hardware, " \
                 "cubic-spline kernel, own geometry)"
@@ -85,10 +91,12 @@ def cpu_baseline(layout, budget_s: float = 12.0):
     }
 
 
-def adjoint_ratio(layout, steps: int, every: int):
+def adjoint_ratio(layout, steps: int, every: int, reps: int = 3):
     """Wall time of the checkpointed backward pass (recompute + adjoint) over
     the forward pass of the same rollout (both on the device, synchronised),
-    and the peak device memory of the pair."""
+    median over `reps` repetitions (small layouts are partly bound by host
+    launch overhead, which varies from run to run), and the peak device
+    memory."""
     import torch
 
     from paper_1110_3711_amd.rollout import Rollout
@@ -104,19 +112,25 @@ def adjoint_ratio(layout, steps: int, every: int):
     xw = warm.forward(layout.phys.alpha, v0)
     warm.backward(torch.ones_like(xw))
     del warm
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    xk = roll.forward(layout.phys.alpha, v0)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    gx = 2.0 / 3.0 * (xk.mean(0) - target) / xk.shape[0]
-    ga, gv = roll.backward(gx.expand_as(xk).contiguous())
-    torch.cuda.synchronize()
-    t2 = time.perf_counter()
+    runs = []
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        xk = roll.forward(layout.phys.alpha, v0)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        gx = 2.0 / 3.0 * (xk.mean(0) - target) / xk.shape[0]
+        ga, gv = roll.backward(gx.expand_as(xk).contiguous())
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        runs.append((t1 - t0, t2 - t1))
+    ratios = [b / f for f, b in runs]
+    k = int(np.argsort(ratios)[len(ratios) // 2])
     ok = bool(torch.isfinite(gv).all().item()) and bool(torch.isfinite(ga).item())
-    return {"workload": layout.name, "particles": layout.n, "ratio": (t2 - t1) / (t1 - t0),
-            "forward_s": t1 - t0, "backward_s": t2 - t1, "steps": steps,
-            "checkpoint_every": every, "finite": ok, "alpha_grad": float(ga.item()),
+    return {"workload": layout.name, "particles": layout.n, "ratio": ratios[k],
+            "ratios": ratios, "forward_s": runs[k][0], "backward_s": runs[k][1],
+            "steps": steps, "checkpoint_every": every, "finite": ok,
+            "alpha_grad": float(ga.item()),
             "peak_device_bytes": int(torch.cuda.max_memory_allocated())}
 
 
@@ -127,6 +141,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--config", default="dam_break_1m")
     ap.add_argument("--nsub", type=int, default=1)
+    ap.add_argument("--kernel", choices=["wendland", "cubic"], default="wendland",
+                    help="smoothing kernel (cubic: the Table 1 spline, with alpha = 0.25)")
+    ap.add_argument("--tensile", action="store_true",
+                    help="tensile correction on (spacing = the layout's dp)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=12.0)
     ap.add_argument("--adjoint-config", default="dam_break_64k",
@@ -154,7 +172,14 @@ def main():
         b.copy_(a)
         torch.cuda.synchronize()
         del a, b
-    lay = named_case(args.config)
+    def variant(layout):
+        if args.kernel == "cubic":
+            layout.phys = dataclasses.replace(layout.phys, kernel=1, alpha=0.25)
+        if args.tensile:
+            layout.phys = dataclasses.replace(layout.phys, tensile_dp=layout.phys.dp)
+        return layout
+
+    lay = variant(named_case(args.config))
     torch.cuda.reset_peak_memory_stats()
     sim = sph.Simulation(lay, nsub=args.nsub)
     stream = torch.cuda.current_stream()
@@ -197,7 +222,15 @@ def main():
 
     # one fused pair-kernel launch per step: fluid targets (F-F + F-B), then
     # boundary targets (B-F)
-    flop_launch = (pf * FLOP_FLUID_PAIR + pb * FLOP_BOUND_PAIR) / K
+    ffl = FLOP_FLUID_PAIR + (FLOP_CUBIC_EXTRA if args.kernel == "cubic" else 0) + \
+        (FLOP_TENSILE_EXTRA if args.tensile else 0)
+    fbd = FLOP_BOUND_PAIR + (FLOP_CUBIC_EXTRA if args.kernel == "cubic" else 0)
+    flop_launch = (pf * ffl + pb * fbd) / K
+    # the committed counter record holds the default kernel (Wendland, no
+    # tensile correction) on the 1M-particle layout only
+    default_path = (args.config == "dam_break_1m" and args.kernel == "wendland" and
+                    not args.tensile and args.nsub == 1)
+    traffic = _traffic_record() if default_path else None
     achieved = flop_launch / (pi_ms.mean() / 1e3)
     roof = {
         "bound": "alu",
@@ -206,12 +239,13 @@ def main():
         "peak": PEAK_FP32_VECTOR / 1e12,
         "unit": "TFLOP/s",
         "frac": achieved / PEAK_FP32_VECTOR,
-        "traffic": _traffic_record(),
+        "traffic": traffic,
+        "traffic_GBps": None if traffic is None else traffic / (pi_ms.mean() / 1e3) / 1e9,
         "avg_launch_ms": float(pi_ms.mean()),
         "pairs_per_launch": (pf + pb) / K,
         "fluid_target_pairs_per_launch": pf / K,
         "boundary_target_pairs_per_launch": pb / K,
-        "flop_per_pair": {"fluid_target": FLOP_FLUID_PAIR, "boundary_target": FLOP_BOUND_PAIR},
+        "flop_per_pair": {"fluid_target": ffl, "boundary_target": fbd},
     }
 
     out = {
@@ -234,7 +268,9 @@ def main():
             "boundary": lay.nb,
             "nsub": args.nsub,
             "cells": sim.ncell,
-            "kernel": "Wendland quintic, h = 1.2 sqrt(3) dp, support 2h",
+            "kernel": ("cubic spline, alpha = 0.25" if args.kernel == "cubic" else
+                       "Wendland quintic") + ", h = 1.2 sqrt(3) dp, support 2h" +
+                      (", tensile correction" if args.tensile else ""),
             "parallelism": "single GPU",
         },
         "steps_per_s": K / t,
@@ -252,7 +288,7 @@ def main():
     if not args.no_adjoint:
         del sim
         torch.cuda.empty_cache()
-        alay = lay if args.adjoint_config == args.config else named_case(args.adjoint_config)
+        alay = lay if args.adjoint_config == args.config else variant(named_case(args.adjoint_config))
         adj = adjoint_ratio(alay, args.adjoint_steps, args.adjoint_every)
         out["adjoint"] = adj
         out["adjoint_forward_ratio"] = adj["ratio"]

@@ -39,14 +39,15 @@ class _Tape:
         self.info = torch.zeros(4, dtype=torch.int32, device=dev)
         self.perm = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
         self.ace = torch.empty((max(n, 1), 4), dtype=torch.float32, device=dev)
+        c = sph.Cells()
+        c.start, c.list, c.info = self.start.data_ptr(), self.list.data_ptr(), self.info.data_ptr()
+        self._cells = c
 
     def state(self) -> sph.State:
         return self.st.c()
 
     def cells(self) -> sph.Cells:
-        c = sph.Cells()
-        c.start, c.list, c.info = self.start.data_ptr(), self.list.data_ptr(), self.info.data_ptr()
-        return c
+        return self._cells
 
 
 def _adjoint_struct(xb, vb, vpb, ab) -> sph.Adjoint:

@@ -268,12 +268,16 @@ class DeviceState:
         self.id = torch.empty(n, dtype=torch.int32, device=device)
 
     def c(self) -> State:
-        s = State()
-        s.n, s.nb = self.n, self.nb
-        s.cell, s.pos = self.cell.data_ptr(), self.pos.data_ptr()
-        s.velrho, s.velrho_prev = self.velrho.data_ptr(), self.velrho_prev.data_ptr()
-        s.id = self.id.data_ptr()
-        return s
+        """The C descriptor of these arrays (built once: the tensors are never
+        reallocated)."""
+        if getattr(self, "_c", None) is None:
+            s = State()
+            s.n, s.nb = self.n, self.nb
+            s.cell, s.pos = self.cell.data_ptr(), self.pos.data_ptr()
+            s.velrho, s.velrho_prev = self.velrho.data_ptr(), self.velrho_prev.data_ptr()
+            s.id = self.id.data_ptr()
+            self._c = s
+        return self._c
 
 
 class Simulation:
@@ -320,9 +324,12 @@ class Simulation:
 
     # -- cells struct
     def cells(self) -> Cells:
-        c = Cells()
-        c.start, c.list, c.info = self.start.data_ptr(), self.list.data_ptr(), self.info.data_ptr()
-        return c
+        if getattr(self, "_cells", None) is None:
+            c = Cells()
+            c.start, c.list, c.info = (self.start.data_ptr(), self.list.data_ptr(),
+                                       self.info.data_ptr())
+            self._cells = c
+        return self._cells
 
     def upload(self, x, v, rho):
         import torch
