@@ -145,9 +145,6 @@ def main():
                     help="smoothing kernel (cubic: the Table 1 spline, with alpha = 0.25)")
     ap.add_argument("--tensile", action="store_true",
                     help="tensile correction on (spacing = the layout's dp)")
-    ap.add_argument("--pairs", choices=["gather", "symmetric"], default="gather",
-                    help="fluid-fluid pairs: evaluated from both ends (gather) or once, "
-                         "with the reaction to the other particle (symmetric, nsub = 1)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=12.0)
     ap.add_argument("--adjoint-config", default="dam_break_64k",
@@ -194,7 +191,6 @@ def main():
     if sim.dev_status() & sph.SPH_DEV_NONFINITE:
         raise SystemExit("non-finite state during warmup")
 
-    pi_parts = sph.SPH_PI_ALL | (sph.SPH_PI_SYMMETRIC if args.pairs == "symmetric" else 0)
     K = args.steps
     npairs = torch.zeros(2, dtype=torch.int64, device=sim.device)  # fluid, boundary targets
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
@@ -207,7 +203,7 @@ def main():
     for k in range(K):
         sim.build_cells()
         ev[k][0].record(stream)
-        sim.interact(parts=pi_parts, npairs=npairs)
+        sim.interact(parts=sph.SPH_PI_ALL, npairs=npairs)
         ev[k][1].record(stream)
         sim.update()
     stop.record(stream)
@@ -233,7 +229,7 @@ def main():
     # the committed counter record holds the default kernel (Wendland, no
     # tensile correction) on the 1M-particle layout only
     default_path = (args.config == "dam_break_1m" and args.kernel == "wendland" and
-                    not args.tensile and args.nsub == 1 and args.pairs == "gather")
+                    not args.tensile and args.nsub == 1)
     traffic = _traffic_record() if default_path else None
     achieved = flop_launch / (pi_ms.mean() / 1e3)
     roof = {
@@ -272,7 +268,6 @@ def main():
             "boundary": lay.nb,
             "nsub": args.nsub,
             "cells": sim.ncell,
-            "pairs": args.pairs,
             "kernel": ("cubic spline, alpha = 0.25" if args.kernel == "cubic" else
                        "Wendland quintic") + ", h = 1.2 sqrt(3) dp, support 2h" +
                       (", tensile correction" if args.tensile else ""),

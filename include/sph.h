@@ -53,7 +53,7 @@
 extern "C" {
 #endif
 
-#define SPH_ABI_VERSION 4 /* 2: two-entry npairs; 3: sph_params.tensile_dp; 4: SPH_PI_SYMMETRIC */
+#define SPH_ABI_VERSION 3 /* 2: two-entry npairs; 3: sph_params.tensile_dp */
 #define SPH_API __attribute__((visibility("default")))
 #define SPH_EXCLUDED INT32_MAX /* cell index of a particle outside the domain */
 
@@ -197,16 +197,6 @@ SPH_API sph_status sph_build_cells(const sph_grid *g, const sph_state *src, sph_
 #define SPH_PI_FLUID 1u    /* fluid targets: F-F + F-B (Section 4.5 fused kernel) */
 #define SPH_PI_BOUNDARY 2u /* boundary targets: B-F, plus zeroing of excluded slots */
 #define SPH_PI_ALL 3u
-/* OR-ed with SPH_PI_FLUID or SPH_PI_ALL (nsub = 1 only, nbr_stats NULL):
- * symmetric evaluation of F-F pairs (Section 3.1 and the "Symmetric" variant
- * of Section 3.4).  Pairs whose other particle lies in one of the 12 cells
- * ahead of the target cell ((dx, +1, 0) and (dx, dy, +1)) are evaluated once;
- * the other particle's terms (momentum negated, continuity and |mu| equal) go
- * to a slot per (direction, particle) in the workspace, and a second kernel
- * adds the slots to each particle's sums in a fixed order.  Same results up
- * to FP32 rounding order, still bitwise reproducible; npairs counts both
- * directed interactions of such a pair. */
-#define SPH_PI_SYMMETRIC 4u
 SPH_API sph_status sph_interact(const sph_grid *g, const sph_params *p, const sph_state *st,
                         const sph_cells *cells, unsigned parts, float *ace, float *visc,
                         unsigned long long *npairs, int32_t *nbr_stats, void *ws,

@@ -82,8 +82,7 @@ def lib():
         L.ora_encode.restype = None
         L.ora_decode.argtypes = [C.c_int, ip, fp, dp, C.c_double, ip, dp]
         L.ora_decode.restype = None
-        L.ora_count_f32.argtypes = [C.c_int, C.c_int, ip, fp, ip, C.c_float, C.c_float, C.c_int,
-                                    ip, u32p]
+        L.ora_count_f32.argtypes = [C.c_int, C.c_int, ip, fp, ip, C.c_float, C.c_float, ip, u32p]
         L.ora_count_f32.restype = C.c_longlong
         L.ora_fprime.argtypes = [pp, C.c_double]
         L.ora_fprime.restype = C.c_double
@@ -271,9 +270,7 @@ def decode(cidx, off, origin, cell, nc):
     return x
 
 
-def count_f32(cidx, off, nb, nc, cellf, rc2f, once=False):
-    """Per-target FP32 neighbour counts and id hashes, and their total;
-    once=True: the decision rule of the symmetric pair evaluation."""
+def count_f32(cidx, off, nb, nc, cellf, rc2f):
     cidx = np.ascontiguousarray(cidx, dtype=np.int32)
     off = np.ascontiguousarray(off, dtype=np.float32).reshape(-1, 3)
     n = cidx.size
@@ -281,8 +278,7 @@ def count_f32(cidx, off, nb, nc, cellf, rc2f, once=False):
     cnt = np.zeros(n, dtype=np.int32)
     hs = np.zeros(n, dtype=np.uint32)
     tot = lib().ora_count_f32(n, nb, _p(cidx, C.c_int32), _p(off, C.c_float), _p(ncv, C.c_int32),
-                              float(cellf), float(rc2f), int(bool(once)), _p(cnt, C.c_int32),
-                              _p(hs, C.c_uint32))
+                              float(cellf), float(rc2f), _p(cnt, C.c_int32), _p(hs, C.c_uint32))
     return cnt, hs, tot
 
 

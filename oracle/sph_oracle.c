@@ -530,15 +530,10 @@ ORA_EXPORT void ora_decode(int n, const int32_t *cellidx, const float *off, cons
  *   r2 = fmaf(rz, rz, fmaf(ry, ry, rx * rx)),  neighbour iff r2 < rc2f,
  * dk = k_b - k_a per axis.  This is the precision in which the GPU path takes
  * the same integer decision, so per-target counts and id hashes
- * (sum of uint32(id * 2654435761)) must agree exactly.
- * once != 0: the rule of the symmetric evaluation of fluid-fluid pairs
- * (Section 3.1; each pair computed once): a fluid pair whose cell offset
- * dk = k_b - k_a has dk_z < 0, or dk_z = 0 and dk_y < 0, is decided in b's
- * frame (target b, candidate a), so that the relation is symmetric; every
- * other pair in a's frame.                                                   */
+ * (sum of uint32(id * 2654435761)) must agree exactly.                      */
 ORA_EXPORT long long ora_count_f32(int n, int nb, const int32_t *cellidx, const float *off,
-                                   const int32_t *nc, float cellf, float rc2f, int once,
-                                   int32_t *count, uint32_t *idhash)
+                                   const int32_t *nc, float cellf, float rc2f, int32_t *count,
+                                   uint32_t *idhash)
 {
     int32_t *kk = (int32_t *)malloc(sizeof(int32_t) * 3 * (size_t)(n > 0 ? n : 1));
     for (int i = 0; i < n; ++i) {
@@ -554,17 +549,15 @@ ORA_EXPORT long long ora_count_f32(int n, int nb, const int32_t *cellidx, const 
         int32_t cnt = 0;
         uint32_t hs = 0;
         if (cellidx[a] != ORA_EXCLUDED) {
+            const float ax = off[3 * a], ay = off[3 * a + 1], az = off[3 * a + 2];
             for (int b = 0; b < n; ++b) {
                 if (b == a || cellidx[b] == ORA_EXCLUDED) continue;
                 if (a < nb && b < nb) continue;
-                const int32_t dky = kk[3 * b + 1] - kk[3 * a + 1], dkz = kk[3 * b + 2] - kk[3 * a + 2];
-                const int behind = once && a >= nb && b >= nb && (dkz < 0 || (dkz == 0 && dky < 0));
-                const int t = behind ? b : a, c = behind ? a : b;  /* frame of t */
-                const float sx = (float)(kk[3 * c] - kk[3 * t]) * cellf;
-                const float sy = (float)(kk[3 * c + 1] - kk[3 * t + 1]) * cellf;
-                const float sz = (float)(kk[3 * c + 2] - kk[3 * t + 2]) * cellf;
-                const float bx = off[3 * c] + sx, by = off[3 * c + 1] + sy, bz = off[3 * c + 2] + sz;
-                const float rx = off[3 * t] - bx, ry = off[3 * t + 1] - by, rz = off[3 * t + 2] - bz;
+                const float sx = (float)(kk[3 * b] - kk[3 * a]) * cellf;
+                const float sy = (float)(kk[3 * b + 1] - kk[3 * a + 1]) * cellf;
+                const float sz = (float)(kk[3 * b + 2] - kk[3 * a + 2]) * cellf;
+                const float bx = off[3 * b] + sx, by = off[3 * b + 1] + sy, bz = off[3 * b + 2] + sz;
+                const float rx = ax - bx, ry = ay - by, rz = az - bz;
                 const float r2 = fmaf(rz, rz, fmaf(ry, ry, rx * rx));
                 if (r2 < rc2f) {
                     ++cnt;

@@ -119,10 +119,7 @@ sph_status sph_interact(const sph_grid *g, const sph_params *p, const sph_state 
                         size_t ws_bytes, hipStream_t stream)
 {
     if (!grid_ok(g) || !params_ok(g, p) || !state_ok(st) || !cells_ok(cells)) return SPH_ERR_ARG;
-    if ((parts & SPH_PI_ALL) == 0 || (parts & ~(SPH_PI_ALL | SPH_PI_SYMMETRIC))) return SPH_ERR_ARG;
-    if ((parts & SPH_PI_SYMMETRIC) &&
-        (!(parts & SPH_PI_FLUID) || g->nsub != 1 || nbr_stats != nullptr))
-        return SPH_ERR_ARG;
+    if (parts == 0 || (parts & ~SPH_PI_ALL)) return SPH_ERR_ARG;
     if (st->n > 0 && (!ace || !visc)) return SPH_ERR_ARG;
     Workspace w;
     const sph_status ws_st = ws_check(g, st->n, ws, ws_bytes, &w);

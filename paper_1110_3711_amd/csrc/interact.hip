@@ -48,11 +48,6 @@ constexpr float kFar = 1.0e30f;      // padding position: never within the suppo
 constexpr int kXcds = 8;             // MI355X: workgroups are dealt to 8 XCDs round robin
 constexpr int kBinBits = 5;          // staged candidates are ordered by 32 bins of x
 constexpr int kBins = 1 << kBinBits;
-// Symmetric evaluation of fluid-fluid pairs (nsub = 1): the 12 forward
-// neighbour cells of a target cell, (dx, +1, 0) and (dx, dy, +1) for
-// dx, dy in {-1, 0, 1}; direction d = dx + 1 for the first row and
-// 3 + 3 (dy + 1) + dx + 1 for the plane above.
-constexpr int kTileSym = 1152;       // LDS: 32 B per candidate + 20 B of reactions
 
 struct RunTable {
     int32_t nruns;
@@ -63,8 +58,6 @@ struct RunTable {
     int32_t dx0[kMaxRuns];                  // x0 - cx
     float sy[kMaxRuns], sz[kMaxRuns];       // dy * cell, dz * cell
     int32_t self_run;                       // run holding the target cell's own fluid particles
-    int32_t dir0[kMaxRuns];                 // symmetric kind: direction of the run's dx = -1
-                                            //   cell for forward fluid runs, else -1
 };
 
 // ---------------------------------------------------------------------------
@@ -217,7 +210,7 @@ __device__ inline uint32_t lds_addr(const void *p)
 
 // Build the run table of target cell (cx, cy, cz).  FLUID: candidates are
 // boundary and fluid particles; otherwise fluid only.
-template <bool FLUID, bool SYM>
+template <bool FLUID>
 __device__ void build_runs(const PairConsts &K, const int32_t *__restrict__ start, int32_t cx,
                            int32_t cy, int32_t cz, RunTable &R)
 {
@@ -234,12 +227,7 @@ __device__ void build_runs(const PairConsts &K, const int32_t *__restrict__ star
         const int rr = r % (side * side);
         const int dy = rr % side - n, dz = rr / side - n;
         const int32_t y = cy + dy, z = cz + dz;
-        // symmetric kind: fluid runs behind the target cell (dz < 0, or dz = 0
-        // and dy < 0) are left out, their pairs come as reactions; the ones
-        // ahead of it (dz > 0, or dz = 0 and dy > 0) give reactions
-        const bool back = SYM && type == 1 && (dz < 0 || (dz == 0 && dy < 0));
-        const bool ahead = SYM && type == 1 && (dz > 0 || (dz == 0 && dy > 0));
-        const bool ok = y >= 0 && y < K.nc1 && z >= 0 && z < K.nc2 && !back;
+        const bool ok = y >= 0 && y < K.nc1 && z >= 0 && z < K.nc2;
         int32_t key0 = 0;
         if (ok) key0 = (type ? K.ncell : 0) + x0 + K.nc0 * (y + K.nc1 * z);
         int32_t s0 = 0, se = 0;
@@ -253,7 +241,6 @@ __device__ void build_runs(const PairConsts &K, const int32_t *__restrict__ star
         R.dx0[r] = x0 - cx;
         R.sy[r] = (float)dy * K.cellf;
         R.sz[r] = (float)dz * K.cellf;
-        R.dir0[r] = ahead ? (dz == 0 ? 0 : 3 + 3 * (dy + 1)) : -1;
         if (type == 1 && dy == 0 && dz == 0) R.self_run = r;
         len = ok ? se - s0 : 0;
     }
@@ -279,11 +266,7 @@ __device__ void build_runs(const PairConsts &K, const int32_t *__restrict__ star
 // pair kernel: forward (targets) and backward (gatherers) share the work
 // queue, the stencil staging and the ballot compaction.
 
-enum Kind {
-    kFwdFluid = 0, kFwdBound = 1, kBwdFluid = 2, kBwdBound = 3, kFwdAll = 4, kBwdAll = 5,
-    kFwdSym = 6,    // fluid targets, fluid-fluid pairs ahead of the cell evaluated once
-    kFwdSymAll = 7  // kFwdSym, then the boundary targets, in one launch
-};
+enum Kind { kFwdFluid = 0, kFwdBound = 1, kBwdFluid = 2, kBwdBound = 3, kFwdAll = 4, kBwdAll = 5 };
 
 struct PairArgs {
     const int32_t *start, *items, *counts;
@@ -299,8 +282,6 @@ struct PairArgs {
     int32_t *queue2;    // fused launches: counter of the boundary work list
     unsigned long long *npairs;  // [2]: += fluid-target, boundary-target pairs
     int32_t *stats;
-    float4 *react;      // symmetric kind: [kSymDirs * n] reactions (a, drho/dt) per direction
-    float *react_v;     // symmetric kind: [kSymDirs * n] their |mu|
 };
 
 // A launch runs one work list (fluid target cells or active boundary cells),
@@ -308,31 +289,20 @@ struct PairArgs {
 // so the short boundary items fill the tail of the launch).
 template <int KIND>
 struct KindTraits {
-    static constexpr bool fused = KIND == kFwdAll || KIND == kBwdAll || KIND == kFwdSymAll;
-    static constexpr bool sym = KIND == kFwdSym || KIND == kFwdSymAll;
+    static constexpr bool fused = KIND == kFwdAll || KIND == kBwdAll;
     static constexpr bool bwd = KIND == kBwdFluid || KIND == kBwdBound || KIND == kBwdAll;
-    static constexpr bool fluid = KIND == kFwdFluid || KIND == kBwdFluid || KIND == kFwdSym || fused;
-    // LDS: 32 B (forward) / 48 B (adjoint) / 52 B (symmetric) per candidate
-    static constexpr int tile = bwd ? 1280 : sym ? kTileSym : kTile;
-    static constexpr int first = fused ? (bwd ? kBwdFluid : sym ? kFwdSym : kFwdFluid) : KIND;
+    static constexpr bool fluid = KIND == kFwdFluid || KIND == kBwdFluid || fused;  // first list
+    static constexpr int tile = bwd ? 1280 : kTile;  // LDS: 32 B (forward) / 48 B per candidate
+    static constexpr int first = fused ? (bwd ? kBwdFluid : kFwdFluid) : KIND;
     static constexpr int second = bwd ? kBwdBound : kFwdBound;
-    // x-bins of the staging sort; the symmetric kind sorts two segments
-    // (gather-only candidates, then the reaction candidates) of kBins each
-    static constexpr int bins = sym ? 2 * kBins : kBins;
 };
 
 // LDS of one workgroup
-template <int TILE, bool BWD, bool STATS, bool SYM>
+template <int TILE, bool BWD, bool STATS>
 struct PairLds {
-    static constexpr int kTileN = TILE;
     static constexpr int STAGE = (TILE + kThreads - 1) / kThreads;
-    static constexpr int NB = SYM ? 2 * kBins : kBins;
-    static constexpr int GAP = SYM ? kWave : 0;  // padding between the two segments
-    float4 sP[TILE + GAP + 2 * kWave];      // (offset in target frame, P/rho^2) + padding
-    float4 sV[TILE + GAP];                  // (v, rho - rho0)
-    // symmetric kind: reactions accumulated per staged slot, (sum of the
-    // pair's a-terms x, y, z, its drho/dt term, max |mu| as bits)
-    float sR[SYM ? 5 : 1][SYM ? TILE + GAP : 1];
+    float4 sP[TILE + 2 * kWave];            // (offset in target frame, P/rho^2) + padding
+    float4 sV[TILE];                        // (v, rho - rho0)
     float4 sA[BWD ? TILE : 1];              // backward: (abar, Dbar), abar = 0 on boundary
     alignas(256) uint16_t sRing[kWaves][kRing];  // 256 bytes per wave
     uint16_t sTrash[kWaves][kWave];         // rejected candidates land here
@@ -340,8 +310,8 @@ struct PairLds {
         uint16_t sMap[TILE];                // fluid targets: staging index -> sorted slot
         float4 sTgt[TILE / 8];              // boundary targets: (pos, velrho) of the first
     };                                      //   TILE / 16 targets of the cell
-    uint16_t sCnt[STAGE][kWaves][NB];
-    int32_t sBin[NB + 1];                   // first sorted slot of each x-bin
+    uint16_t sCnt[STAGE][kWaves][kBins];
+    int32_t sBin[kBins + 1];                // first sorted slot of each x-bin
     int32_t sSlot[STATS ? TILE : 1];        // candidate slot (diagnostics only)
     RunTable R;
     int32_t sItem;
@@ -366,11 +336,8 @@ __device__ __forceinline__ void pair_item(const PairConsts &K, const PairArgs &A
     using T = KindTraits<KIND>;
     constexpr bool FLUID = T::fluid;
     constexpr bool BWD = T::bwd;
-    constexpr bool SYM = T::sym;
-    constexpr int TILE = L::kTileN;
+    constexpr int TILE = T::tile;
     constexpr int STAGE = L::STAGE;
-    constexpr int NBK = T::bins;  // x-bins of this kind (<= L::NB)
-    constexpr int RS = SYM ? TILE + L::GAP : 1;  // stride of the reaction components
     auto &sP = S.sP;
     auto &sV = S.sV;
     auto &sA = S.sA;
@@ -390,7 +357,7 @@ __device__ __forceinline__ void pair_item(const PairConsts &K, const PairArgs &A
     const int32_t tbeg = __builtin_amdgcn_readfirstlane(min(max(A.start[key], 0), K.n));
     const int32_t tend = __builtin_amdgcn_readfirstlane(min(max(A.start[key + 1], tbeg), K.n));
 
-    build_runs<FLUID, SYM>(K, A.start, cx, cy, cz, R);
+    build_runs<FLUID>(K, A.start, cx, cy, cz, R);
     const int32_t total = __builtin_amdgcn_readfirstlane(R.total);
     const int nr = __builtin_amdgcn_readfirstlane(R.nruns);
     const int nbruns = FLUID ? nr / 2 : 0;  // runs [0, nbruns) hold boundary particles
@@ -422,7 +389,7 @@ __device__ __forceinline__ void pair_item(const PairConsts &K, const PairArgs &A
         auto rank_round = [&](int u, int bin) {
             const bool valid = (int32_t)(threadIdx.x + u * kThreads) < tlen;
             unsigned long long peers = ballot(valid);
-            for (int b = 0; b < (SYM ? kBinBits + 1 : kBinBits); ++b) {
+            for (int b = 0; b < kBinBits; ++b) {
                 const bool bit = (bin >> b) & 1;
                 const unsigned long long mb = ballot(bit);
                 peers &= bit ? mb : ~mb;
@@ -439,7 +406,7 @@ __device__ __forceinline__ void pair_item(const PairConsts &K, const PairArgs &A
             S.sTgt[2 * threadIdx.x] = A.pos[tbeg + threadIdx.x];
             S.sTgt[2 * threadIdx.x + 1] = A.velrho[tbeg + threadIdx.x];
         }
-        for (int i = threadIdx.x; i < STAGE * kWaves * L::NB; i += kThreads)
+        for (int i = threadIdx.x; i < STAGE * kWaves * kBins; i += kThreads)
             (&sCnt[0][0][0])[i] = 0;
         // pass A: locate all of this thread's candidates, then one round of loads
         int32_t j0 = 0, j1 = 0, j2 = 0, j3 = 0;
@@ -450,19 +417,17 @@ __device__ __forceinline__ void pair_item(const PairConsts &K, const PairArgs &A
         if (STAGE > 3) locate(threadIdx.x + 3 * kThreads, j3, q3);
         const float x0 = A.pos[j0].x, x1 = STAGE > 1 ? A.pos[j1].x : 0.f,
                     x2 = STAGE > 2 ? A.pos[j2].x : 0.f, x3 = STAGE > 3 ? A.pos[j3].x : 0.f;
-        // symmetric kind: reaction candidates form the second segment
-        auto seg = [&](int run) { return SYM && R.dir0[run] >= 0 ? kBins : 0; };
-        const int bn0 = xbin(x0 + shift_x(j0, q0)) + seg(q0);
-        const int bn1 = STAGE > 1 ? xbin(x1 + shift_x(j1, q1)) + seg(q1) : 0;
-        const int bn2 = STAGE > 2 ? xbin(x2 + shift_x(j2, q2)) + seg(q2) : 0;
-        const int bn3 = STAGE > 3 ? xbin(x3 + shift_x(j3, q3)) + seg(q3) : 0;
+        const int bn0 = xbin(x0 + shift_x(j0, q0));
+        const int bn1 = STAGE > 1 ? xbin(x1 + shift_x(j1, q1)) : 0;
+        const int bn2 = STAGE > 2 ? xbin(x2 + shift_x(j2, q2)) : 0;
+        const int bn3 = STAGE > 3 ? xbin(x3 + shift_x(j3, q3)) : 0;
         __syncthreads();
         const int rk0 = rank_round(0, bn0);
         const int rk1 = STAGE > 1 ? rank_round(1, bn1) : 0;
         const int rk2 = STAGE > 2 ? rank_round(2, bn2) : 0;
         const int rk3 = STAGE > 3 ? rank_round(3, bn3) : 0;
         __syncthreads();
-        if ((int)threadIdx.x < NBK) {  // per-bin offsets over (round, wave)
+        if ((int)threadIdx.x < kBins) {  // per-bin offsets over (round, wave)
             const int b = threadIdx.x;
             int run = 0;
             for (int u = 0; u < STAGE; ++u)
@@ -475,16 +440,13 @@ __device__ __forceinline__ void pair_item(const PairConsts &K, const PairArgs &A
         }
         __syncthreads();
         if (threadIdx.x < kWave) {  // bin starts: exclusive scan of the bin totals
-            static_assert(NBK <= kWave, "one wavefront scans the bins");
             const int ln = threadIdx.x;
-            int32_t v = ln < NBK ? sBin[ln + 1] : 0;
+            int32_t v = ln < kBins ? sBin[ln + 1] : 0;
             for (int o = 1; o < kWave; o <<= 1) {
                 const int32_t t = __shfl_up(v, o);
                 if (ln >= o) v += t;
             }
-            // symmetric kind: kWave padding entries between the segments
-            if (SYM && ln >= kBins - 1) v += kWave;
-            if (ln < NBK) sBin[ln + 1] = v;
+            if (ln < kBins) sBin[ln + 1] = v;
             if (ln == 0) sBin[0] = 0;
         }
         __syncthreads();
@@ -506,27 +468,13 @@ __device__ __forceinline__ void pair_item(const PairConsts &K, const PairArgs &A
             }
             if (STATS) sSlot[slot] = j;
             if (FLUID) sMap[l] = (uint16_t)slot;
-            if (SYM) {
-#pragma unroll
-                for (int k = 0; k < 5; ++k) S.sR[k][slot] = 0.f;
-            }
         };
         place(0, j0, q0, bn0, rk0);
         if (STAGE > 1) place(1, j1, q1, bn1, rk1);
         if (STAGE > 2) place(2, j2, q2, bn2, rk2);
         if (STAGE > 3) place(3, j3, q3, bn3, rk3);
-        if (SYM) {
-            // padding after each segment: a window rounded up to whole chunks
-            // never tests a candidate of the other segment
-            const int32_t ea = sBin[kBins] - kWave, eb = sBin[NBK];
-            if (threadIdx.x < kWave) sP[ea + threadIdx.x] = make_float4(kFar, kFar, kFar, 0.f);
-            if (threadIdx.x < 2 * kWave) sP[eb + threadIdx.x] = make_float4(kFar, kFar, kFar, 0.f);
-        } else if (threadIdx.x < 2 * kWave) {
-            sP[tlen + threadIdx.x] = make_float4(kFar, kFar, kFar, 0.f);
-        }
+        if (threadIdx.x < 2 * kWave) sP[tlen + threadIdx.x] = make_float4(kFar, kFar, kFar, 0.f);
         __syncthreads();
-        // symmetric kind: byte offset of the first reaction candidate
-        const uint32_t segb = SYM ? (uint32_t)__builtin_amdgcn_readfirstlane(sBin[kBins]) << 4 : 0u;
 
         // ---- one wavefront per target
         const int32_t selfbase =
@@ -630,18 +578,6 @@ __device__ __forceinline__ void pair_item(const PairConsts &K, const PairArgs &A
                         s0 = __builtin_fmaf(coef, rx, s0);
                         s1 = __builtin_fmaf(coef, ry, s1);
                         s2 = __builtin_fmaf(coef, rz, s2);
-                        // symmetric kind: the pair's terms for candidate b are
-                        // those of a with the momentum term negated (grad_b W_ba =
-                        // -grad_a W_ab, Pi symmetric), kept here unscaled
-                        if (SYM && off >= segb) {
-                            float *rb = &S.sR[0][0] + (off >> 4);
-                            __hip_atomic_fetch_add(rb, coef * rx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-                            __hip_atomic_fetch_add(rb + RS, coef * ry, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-                            __hip_atomic_fetch_add(rb + 2 * RS, coef * rz, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-                            __hip_atomic_fetch_add(rb + 3 * RS, vdr * G, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-                            __hip_atomic_fetch_max((unsigned *)(rb + 4 * RS), __builtin_bit_cast(unsigned, fabsf(u)),
-                                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-                        }
                     }
                     if (STATS) hs += (uint32_t)A.ids[sSlot[off >> 4]] * 2654435761u;
                 } else {
@@ -732,30 +668,20 @@ __device__ __forceinline__ void pair_item(const PairConsts &K, const PairArgs &A
             // Two chunks per iteration, both loaded up front: the second read
             // ends before tlen + 2 * kWave, inside the padding.
             // (wave-uniform: every lane holds the same target)
-            const int xb0 = xbin(pa.x - K.xwin), xb1 = xbin(pa.x + K.xwin) + 1;
-            auto scan = [&](int seg0) {
-                const int32_t w0 = __builtin_amdgcn_readfirstlane(sBin[seg0 + xb0]);
-                // (symmetric kind: sBin[kBins] starts the second segment, the
-                // first one ends kWave padding entries before it)
-                const int32_t w1 = __builtin_amdgcn_readfirstlane(
-                    sBin[seg0 + xb1] - (SYM && seg0 + xb1 == kBins ? kWave : 0));
-                const int32_t wend = w0 + ((w1 - w0 + kWave - 1) & ~(kWave - 1));
-                for (int32_t cb0 = w0; cb0 < wend; cb0 += 2 * kWave) {
-                    const float4 c0 = sP[cb0 + lane];
-                    const float4 c1 = sP[cb0 + kWave + lane];
-                    chunk(c0, cb0);
-                    if (cb0 + kWave < wend) chunk(c1, cb0 + kWave);
-                }
-            };
-            scan(0);
-            const int wpa = wp;  // pairs of the first segment
-            if (SYM) scan(kBins);
+            const int32_t w0 = __builtin_amdgcn_readfirstlane(sBin[xbin(pa.x - K.xwin)]);
+            const int32_t w1 = __builtin_amdgcn_readfirstlane(sBin[xbin(pa.x + K.xwin) + 1]);
+            const int32_t wend = w0 + ((w1 - w0 + kWave - 1) & ~(kWave - 1));
+            for (int32_t cb0 = w0; cb0 < wend; cb0 += 2 * kWave) {
+                const float4 c0 = sP[cb0 + lane];
+                const float4 c1 = sP[cb0 + kWave + lane];
+                chunk(c0, cb0);
+                if (cb0 + kWave < wend) chunk(c1, cb0 + kWave);
+            }
             if (wp > rp) {
                 __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
                 if (lane < wp - rp) pair(*(const lds_u16 *)(uintptr_t)raddr);
             }
-            // a reaction pair is two directed interactions
-            const int cnt = wp - (self_here ? 1 : 0) + (SYM ? wp - wpa : 0);
+            const int cnt = wp - (self_here ? 1 : 0);
             pairs_acc += (unsigned long long)cnt;
 
             // ---- reduce over the wave, write (first tile) or accumulate
@@ -828,26 +754,6 @@ __device__ __forceinline__ void pair_item(const PairConsts &K, const PairArgs &A
             }
         }
         __syncthreads();
-        if (SYM) {
-            // reactions of this tile's candidates ahead of the cell, scaled like
-            // the targets' own sums, to the slot of their direction
-            for (int32_t l = threadIdx.x; l < tlen; l += kThreads) {
-                int32_t j;
-                int run;
-                locate(l, j, run);
-                const int d0 = R.dir0[run];
-                if (d0 < 0) continue;
-                int ci = 0;
-                for (int i = 1; i < R.ncx[run]; ++i) ci += R.s[run][i] <= j ? 1 : 0;
-                const int d = min(max(d0 + R.dx0[run] + ci + 1, 0), kSymDirs - 1);
-                const int slot = sMap[l];
-                const int64_t o = (int64_t)d * K.n + j;
-                A.react[o] = make_float4(K.mgs * S.sR[0][slot], K.mgs * S.sR[1][slot],
-                                         K.mgs * S.sR[2][slot], K.mgs * S.sR[3][slot]);
-                A.react_v[o] = K.h * S.sR[4][slot];
-            }
-            __syncthreads();
-        }
     }
 }
 
@@ -855,7 +761,7 @@ template <int KIND, bool STATS, int KER, bool TENS>
 __global__ __launch_bounds__(kThreads) void k_interact(PairConsts K, PairArgs A)
 {
     using T = KindTraits<KIND>;
-    __shared__ PairLds<T::tile, T::bwd, STATS, T::sym> S;
+    __shared__ PairLds<T::tile, T::bwd, STATS> S;
     LaneCtx C;
     C.lane = threadIdx.x & (kWave - 1);
     C.wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
@@ -954,57 +860,6 @@ __global__ __launch_bounds__(kThreads) void k_interact(PairConsts K, PairArgs A)
     if (A.npairs && C.lane == 0) {
         if (p1) atomicAdd(A.npairs + (T::fluid ? 0 : 1), p1);
         if (p2) atomicAdd(A.npairs + 1, p2);
-    }
-}
-
-// Symmetric kind, second kernel: every fluid particle adds the reactions of
-// the (up to 12) non-empty fluid cells behind it, in the fixed order of the
-// directions, to its own sums.  One wavefront per fluid cell; the slot of
-// direction d was written by the item of cell (cell - offset(d)) exactly when
-// that cell holds fluid.
-__global__ __launch_bounds__(256) void k_react_gather(PairConsts K, const int32_t *__restrict__ start,
-                                                      const int32_t *__restrict__ list,
-                                                      const int32_t *__restrict__ info, float4 *ace,
-                                                      float *visc, const float4 *__restrict__ react,
-                                                      const float *__restrict__ react_v)
-{
-    const int lane = threadIdx.x & (kWave - 1);
-    const int32_t ib = min(max(info[0], 0), K.n);
-    const int32_t nf = min(max(info[1], 0), K.n - ib);
-    const int wpb = blockDim.x / kWave;
-    for (int32_t w = blockIdx.x * wpb + threadIdx.x / kWave; w < nf; w += gridDim.x * wpb) {
-        const int32_t c = min(max(list[ib + w] - K.ncell, 0), K.ncell - 1);
-        const int32_t cx = c % K.nc0, cy = (c / K.nc0) % K.nc1, cz = c / (K.nc0 * K.nc1);
-        bool src = false;
-        if (lane < kSymDirs) {
-            const int dz = lane < 3 ? 0 : 1;
-            const int dy = lane < 3 ? 1 : (lane - 3) / 3 - 1;
-            const int dx = (lane < 3 ? lane : (lane - 3) % 3) - 1;
-            const int32_t sx = cx - dx, sy = cy - dy, sz = cz - dz;
-            if (sx >= 0 && sx < K.nc0 && sy >= 0 && sy < K.nc1 && sz >= 0 && sz < K.nc2) {
-                const int32_t key = K.ncell + sx + K.nc0 * (sy + K.nc1 * sz);
-                src = start[key] < start[key + 1];
-            }
-        }
-        const unsigned long long m = ballot(src);
-        const int32_t key = K.ncell + c;
-        const int32_t b0 = min(max(start[key], 0), K.n), b1 = min(max(start[key + 1], b0), K.n);
-        for (int32_t i = b0 + lane; i < b1; i += kWave) {
-            float4 a = ace[i];
-            float v = visc[i];
-            for (int d = 0; d < kSymDirs; ++d) {
-                if (!((m >> d) & 1ull)) continue;
-                const int64_t o = (int64_t)d * K.n + i;
-                const float4 r = react[o];
-                a.x += r.x;
-                a.y += r.y;
-                a.z += r.z;
-                a.w += r.w;
-                v = fmaxf(v, react_v[o]);
-            }
-            ace[i] = a;
-            visc[i] = v;
-        }
     }
 }
 
@@ -1183,8 +1038,6 @@ static PairArgs base_args(const sph_state *st, const sph_cells *cells)
     A.queue2 = nullptr;
     A.npairs = nullptr;
     A.stats = nullptr;
-    A.react = nullptr;
-    A.react_v = nullptr;
     return A;
 }
 
@@ -1204,17 +1057,6 @@ hipError_t launch_interact(const sph_grid *g, const sph_params *p, const sph_sta
     // boundary launch or [8] the boundary counter of the fused launch, [16]
     // active boundary cells
     const bool stats = nbr_stats != nullptr;
-    const bool sym = (parts & SPH_PI_SYMMETRIC) != 0;
-    parts &= SPH_PI_ALL;
-    A.react = w.react;
-    A.react_v = w.react_v;
-    // symmetric kind: the fluid targets' sums are complete once every item
-    // has written its reactions
-    auto gather = [&]() {
-        k_react_gather<<<2048, 256, 0, s>>>(K, cells->start, cells->list, cells->info,
-                                            (float4 *)ace, visc, w.react, w.react_v);
-        return hipGetLastError();
-    };
     k_zero_counters<<<1, 64, 0, s>>>(w.counters, 17);
     if (parts & SPH_PI_BOUNDARY)
         k_bound_filter<<<256, 256, 0, s>>>(K, cells->start, cells->list, cells->info, w.active,
@@ -1224,15 +1066,12 @@ hipError_t launch_interact(const sph_grid *g, const sph_params *p, const sph_sta
         A.items2 = w.active;
         A.counts2 = w.counters + 16;
         A.queue2 = w.counters + 8;
-        if (!sym) return launch_kind<kFwdAll>(K, A, stats, s);
-        const hipError_t e = launch_kind<kFwdSymAll>(K, A, false, s);
-        return e != hipSuccess ? e : gather();
+        return launch_kind<kFwdAll>(K, A, stats, s);
     }
     hipError_t e = hipSuccess;
     if (parts & SPH_PI_FLUID) {
         A.queue = w.counters;
-        e = sym ? launch_kind<kFwdSym>(K, A, false, s) : launch_kind<kFwdFluid>(K, A, stats, s);
-        if (e == hipSuccess && sym) e = gather();
+        e = launch_kind<kFwdFluid>(K, A, stats, s);
         if (e != hipSuccess) return e;
     }
     if (parts & SPH_PI_BOUNDARY) {

@@ -19,7 +19,6 @@ constexpr int kScanItems = 16;
 constexpr int kScanTile = kScanThreads * kScanItems;
 constexpr int kReduceThreads = 256;
 constexpr int kReduceBlocksMax = 1024;
-constexpr int kSymDirs = 12;         // forward neighbour cells of the symmetric pair kind
 
 inline int64_t ncell_of(const sph_grid *g)
 {
@@ -38,8 +37,6 @@ struct Workspace {
     int32_t *active;                          // [n] boundary cells with fluid in reach
     float *alpha_part;                        // [n] per-slot alpha adjoint
     double *reduce;                           // [3 * kReduceBlocksMax] CFL partials
-    float4 *react;                            // nsub = 1: [kSymDirs * n] pair reactions
-    float *react_v;                           // nsub = 1: [kSymDirs * n] their |mu|
     size_t bytes;
 };
 
@@ -72,9 +69,6 @@ inline bool layout_workspace(const sph_grid *g, int64_t n, void *base, Workspace
     const size_t o_a = take(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
     const size_t o_ap = take(sizeof(float) * (size_t)(n > 0 ? n : 1));
     const size_t o_r = take(sizeof(double) * 3 * kReduceBlocksMax);
-    const size_t nreact = g->nsub == 1 ? (size_t)kSymDirs * (size_t)(n > 0 ? n : 1) : 1;
-    const size_t o_rx = take(sizeof(float4) * nreact);
-    const size_t o_rv = take(sizeof(float) * nreact);
     w->bytes = off;
     if (base) {
         char *b = (char *)base;
@@ -89,8 +83,6 @@ inline bool layout_workspace(const sph_grid *g, int64_t n, void *base, Workspace
         w->active = (int32_t *)(b + o_a);
         w->alpha_part = (float *)(b + o_ap);
         w->reduce = (double *)(b + o_r);
-        w->react = (float4 *)(b + o_rx);
-        w->react_v = (float *)(b + o_rv);
     }
     return true;
 }

@@ -19,9 +19,9 @@ LIB_PATH = os.path.join(HERE, "libsph.so")
 SPH_OK, SPH_ERR_ARG, SPH_ERR_WORKSPACE, SPH_ERR_HIP = 0, 1, 2, 3
 SPH_DEV_OUT_OF_GRID, SPH_DEV_NONFINITE = 1, 2
 SPH_FIXED_DT, SPH_ADJOINT = 1, 2
-SPH_PI_FLUID, SPH_PI_BOUNDARY, SPH_PI_ALL, SPH_PI_SYMMETRIC = 1, 2, 3, 4
+SPH_PI_FLUID, SPH_PI_BOUNDARY, SPH_PI_ALL = 1, 2, 3
 SPH_EXCLUDED = 2**31 - 1
-ABI_VERSION = 4
+ABI_VERSION = 3
 
 EXPORTS = ["sph_workspace_bytes", "sph_abi_version", "sph_encode", "sph_decode",
            "sph_build_cells", "sph_interact", "sph_step", "sph_interact_backward",

@@ -37,7 +37,7 @@ def test_library_exports_every_declared_symbol(lib):
     for name in _declared():
         assert hasattr(lib, name), name
     assert sorted(sph.EXPORTS) == _declared()
-    assert lib.sph_abi_version() == 4
+    assert lib.sph_abi_version() == 3
 
 
 def _grid():
@@ -57,9 +57,6 @@ def test_workspace_query(lib):
     small = sph.make_grid([0, 0, 0], [1, 1, 1], 0.01, [20, 20, 20], 1)  # does not cover
     assert sph.sph_workspace_bytes(small, 1000) == 0
     assert sph.sph_workspace_bytes(g, -1) == 0
-    # nsub = 1 holds the 12 reaction slots (20 B each) per particle of the
-    # symmetric pair evaluation
-    assert sph.sph_workspace_bytes(g, 2000) - sph.sph_workspace_bytes(g, 1000) >= 240 * 1000
 
 
 def test_validation_errors_before_any_device_work(lib):
@@ -92,21 +89,10 @@ def test_validation_errors_before_any_device_work(lib):
     p2 = sph.make_params(physics(0.02))  # 2h = 0.083 > 0.05
     assert lib.sph_interact(C.byref(g), C.byref(p2), C.byref(st), C.byref(cells), 3, fake, fake,
                             None, None, fake, 1 << 40, None) == sph.SPH_ERR_ARG
-    # unknown parts selectors; the symmetric flag needs the fluid part, nsub = 1
-    # and no per-slot statistics
-    for parts in (0, 8, 3 | 8, sph.SPH_PI_SYMMETRIC, sph.SPH_PI_BOUNDARY | sph.SPH_PI_SYMMETRIC):
+    # unknown parts selectors
+    for parts in (0, 4, 8, 3 | 4, 3 | 8):
         assert lib.sph_interact(C.byref(g), C.byref(p), C.byref(st), C.byref(cells), parts, fake,
                                 fake, None, None, fake, 1 << 40, None) == sph.SPH_ERR_ARG
-    sym = sph.SPH_PI_ALL | sph.SPH_PI_SYMMETRIC
-    assert lib.sph_interact(C.byref(g), C.byref(p), C.byref(st), C.byref(cells), sym, fake, fake,
-                            None, fake, fake, 1 << 40, None) == sph.SPH_ERR_ARG
-    g2 = sph.make_grid([0, 0, 0], [1, 1, 1], 0.025, [40, 40, 40], 2)
-    assert lib.sph_interact(C.byref(g2), C.byref(p), C.byref(st), C.byref(cells), sym, fake, fake,
-                            None, None, fake, 1 << 40, None) == sph.SPH_ERR_ARG
-    # with a workspace that is too small the symmetric call gets as far as
-    # the workspace check (its arguments are valid)
-    assert lib.sph_interact(C.byref(g), C.byref(p), C.byref(st), C.byref(cells), sym, fake, fake,
-                            None, None, fake, 8, None) == sph.SPH_ERR_WORKSPACE
     # gamma other than 7 and unknown kernels are rejected
     p3 = sph.make_params(physics(0.01))
     p3.gamma = 5.0

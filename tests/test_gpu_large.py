@@ -13,7 +13,7 @@ from sph_inputs import SEED_BASE, dam_break
 pytestmark = pytest.mark.gpu
 
 
-def _subset_parity(ora, lay, nsub, nsample=65536, seed=0, symmetric=False):
+def _subset_parity(ora, lay, nsub, nsample=65536, seed=0):
     import torch
 
     from paper_1110_3711_amd import sph
@@ -21,7 +21,7 @@ def _subset_parity(ora, lay, nsub, nsample=65536, seed=0, symmetric=False):
     sim = sph.Simulation(lay, nsub=nsub)
     sim.build_cells()
     sim.npairs.zero_()
-    sim.interact(parts=sph.SPH_PI_ALL | (sph.SPH_PI_SYMMETRIC if symmetric else 0))
+    sim.interact()
     torch.cuda.synchronize()
     ace = sim.by_id(sim.ace)
     visc = sim.by_id(sim.visc)
@@ -51,11 +51,10 @@ def _grid(lay, nsub):
     return org, cell, nc
 
 
-@pytest.mark.parametrize("symmetric", [False, True], ids=["gather", "symmetric"])
-def test_bench_layout_subset_parity(ora, symmetric):
+def test_bench_layout_subset_parity(ora):
     lay = dam_break(0.002, SEED_BASE + 2, vel_sigma=0.05, vel_seed=SEED_BASE + 20, name="dam_break_1m+v")
-    print(f"large: 1.65M-particle dam break symmetric={symmetric}", flush=True)
-    e = _subset_parity(ora, lay, 1, symmetric=symmetric)
+    print("large: 1.65M-particle dam break", flush=True)
+    e = _subset_parity(ora, lay, 1)
     assert max(e) <= 1e-4
 
 

@@ -95,50 +95,6 @@ def test_fp32_decision_matches_fp64_sets(ora):
             assert s == int(hs[a])
 
 
-def test_fp32_once_rule(ora):
-    """The decision rule of the symmetric pair evaluation (each fluid pair
-    decided once, in the frame of the cell it is computed from): the relation
-    is symmetric, it differs from the per-target rule only on pairs within
-    rounding of the cutoff, and pairs with a boundary particle keep the
-    per-target decision."""
-    L = named_case("dam_break_8k")
-    B = blob(14, 0.01, 7, jitter=0.45)
-    for lay in (L, B):
-        org, cell, nc = cell_grid(lay, 1)
-        cidx, off = ora.encode(lay.x, org, cell, nc, lay.lo, lay.hi)
-        rc2 = np.float32(4.0 * lay.phys.h * lay.phys.h)
-        c1, h1, t1 = ora.count_f32(cidx, off, lay.nb, nc, np.float32(cell), rc2)
-        c2, h2, t2 = ora.count_f32(cidx, off, lay.nb, nc, np.float32(cell), rc2, once=True)
-        assert t2 == int(c2.sum())
-        # symmetric relation among the fluid: the sum over targets of the
-        # neighbours' id hashes equals the sum of each target's own hash times
-        # its count (mod 2^32); boundary targets and their fluid pairs are
-        # taken out with the per-target rule, which they keep
-        ids = np.arange(lay.n, dtype=np.uint64)
-        hh = (ids * np.uint64(2654435761)) & np.uint64(0xFFFFFFFF)
-        nb = lay.nb
-        assert np.array_equal(c1[:nb], c2[:nb]) and np.array_equal(h1[:nb], h2[:nb])
-        x = ora.decode(cidx, off, org, cell, nc)
-        fb = 0  # sum over fluid targets of the hashes of their boundary neighbours
-        fcount = c2[nb:].astype(np.int64).copy()
-        if nb:
-            rp, cols = ora.neighbour_csr(x, nb, lay.phys.h, mode=1)
-            for a in range(nb):
-                cb = cols[rp[a]:rp[a + 1]]
-                fb = (fb + int(hh[a]) * cb.size) & 0xFFFFFFFF
-                np.subtract.at(fcount, cb - nb, 1)
-        lhs = (int(h2[nb:].astype(np.uint64).sum()) - fb) & 0xFFFFFFFF
-        rhs = int((fcount.astype(np.uint64) * hh[nb:]).sum()) & 0xFFFFFFFF
-        assert lhs == rhs
-        # the two rules differ only on pairs within rounding of the cutoff
-        bad = np.nonzero(c1 != c2)[0]
-        for a in bad:
-            d2 = ((x[a] - x) ** 2).sum(1)
-            near = np.abs(d2 / (4 * lay.phys.h**2) - 1.0) < 1e-6
-            assert abs(int(c1[a]) - int(c2[a])) <= near.sum()
-        assert len(bad) <= 8
-
-
 def test_stencil_superset(ora):
     # With offsets |o| <= cell/2, a pair inside the support lies within
     # (2 nsub + 1)^3 cells: check every FP64 neighbour pair of the 8k-fluid dam break.
