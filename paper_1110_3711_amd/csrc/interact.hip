@@ -228,14 +228,21 @@ __device__ void build_runs(const PairConsts &K, const int32_t *__restrict__ star
         const int dy = rr % side - n, dz = rr / side - n;
         const int32_t y = cy + dy, z = cz + dz;
         const bool ok = y >= 0 && y < K.nc1 && z >= 0 && z < K.nc2;
+        // key of the run's first cell; key0 + ncx <= 2 ncell, and 0 + ncx
+        // <= ncell for a run outside the grid, so the loads below are in
+        // bounds unconditionally and are all issued before the first use
         int32_t key0 = 0;
         if (ok) key0 = (type ? K.ncell : 0) + x0 + K.nc0 * (y + K.nc1 * z);
+        int32_t sv[kMaxRunCells + 1];
+#pragma unroll
+        for (int i = 0; i <= kMaxRunCells; ++i) sv[i] = start[key0 + min(i, ncx)];
         int32_t s0 = 0, se = 0;
+#pragma unroll
         for (int i = 0; i <= kMaxRunCells; ++i) {
-            const int32_t sv = ok ? start[key0 + min(i, ncx)] : 0;
-            R.s[r][i] = sv;
-            if (i == 0) s0 = sv;
-            if (i == ncx) se = sv;
+            const int32_t v = ok ? sv[i] : 0;
+            R.s[r][i] = v;
+            if (i == 0) s0 = v;
+            if (i == ncx) se = v;
         }
         R.ncx[r] = ok ? ncx : 0;
         R.dx0[r] = x0 - cx;
@@ -403,8 +410,9 @@ __device__ __forceinline__ void pair_item(const PairConsts &K, const PairArgs &A
         // cell's first kTgt targets with the candidates
         constexpr int32_t kTgt = TILE / 16;
         if (!FLUID && tb == 0 && (int32_t)threadIdx.x < min(tend - tbeg, kTgt)) {
-            S.sTgt[2 * threadIdx.x] = A.pos[tbeg + threadIdx.x];
-            S.sTgt[2 * threadIdx.x + 1] = A.velrho[tbeg + threadIdx.x];
+            const float4 tp = A.pos[tbeg + threadIdx.x], tv = A.velrho[tbeg + threadIdx.x];
+            S.sTgt[2 * threadIdx.x] = tp;
+            S.sTgt[2 * threadIdx.x + 1] = tv;
         }
         for (int i = threadIdx.x; i < STAGE * kWaves * kBins; i += kThreads)
             (&sCnt[0][0][0])[i] = 0;
@@ -757,8 +765,15 @@ __device__ __forceinline__ void pair_item(const PairConsts &K, const PairArgs &A
     }
 }
 
+// Four waves per SIMD (two workgroups per CU) is what the LDS allows, and the
+// kernel needs them to hide its LDS and memory latency; at 129+ VGPRs only
+// three fit (about 1.6x the time).  The tensile adjoint is held to 128 VGPRs
+// (without spills); the other instantiations fit by themselves, and the
+// constraint would cost them 1-2% of scheduling freedom.
 template <int KIND, bool STATS, int KER, bool TENS>
-__global__ __launch_bounds__(kThreads) void k_interact(PairConsts K, PairArgs A)
+__global__ __launch_bounds__(kThreads)
+__attribute__((amdgpu_waves_per_eu(KindTraits<KIND>::bwd && TENS ? 4 : 1, 4))) void k_interact(
+    PairConsts K, PairArgs A)
 {
     using T = KindTraits<KIND>;
     __shared__ PairLds<T::tile, T::bwd, STATS> S;
