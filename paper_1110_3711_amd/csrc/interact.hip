@@ -879,47 +879,60 @@ __attribute__((amdgpu_waves_per_eu(KindTraits<KIND>::bwd && TENS ? 4 : 1, 4))) v
 }
 
 // Boundary cells: those with fluid particles in their stencil go to the work
-// list of the B-F pass; the others have no neighbours and get zero outputs,
-// as do excluded particles (forward only: ace != NULL).
+// list of the B-F pass.  Forward only (ace != NULL): every boundary slot and
+// every excluded slot first gets zero outputs (coalesced, one thread per
+// slot); the boundary items of the pair kernel, which run after this kernel
+// on the same stream, overwrite the targets of the active cells.
+template <int NSUB>
+__device__ inline int32_t fluid_in_reach(const PairConsts &K, const int32_t *__restrict__ start,
+                                         int32_t key)
+{
+    const int32_t cx = key % K.nc0, cy = (key / K.nc0) % K.nc1, cz = key / (K.nc0 * K.nc1);
+    const int32_t x0 = max(cx - NSUB, 0), x1 = min(cx + NSUB, K.nc0 - 1);
+    int32_t total = 0;
+#pragma unroll
+    for (int dz = -NSUB; dz <= NSUB; ++dz)
+#pragma unroll
+        for (int dy = -NSUB; dy <= NSUB; ++dy) {
+            const int32_t y = cy + dy, z = cz + dz;
+            const bool ok = y >= 0 && y < K.nc1 && z >= 0 && z < K.nc2;
+            // an out-of-grid run reads start[0] twice (in bounds, difference 0)
+            const int32_t k0 = ok ? K.ncell + x0 + K.nc0 * (y + K.nc1 * z) : 0;
+            const int32_t len = ok ? x1 - x0 + 1 : 0;
+            total += start[k0 + len] - start[k0];
+        }
+    return total;
+}
+
 __global__ void k_bound_filter(PairConsts K, const int32_t *__restrict__ start,
                                const int32_t *__restrict__ list, const int32_t *__restrict__ info,
                                int32_t *__restrict__ active, int32_t *__restrict__ nactive,
                                float4 *__restrict__ ace, float *__restrict__ visc,
                                int32_t *__restrict__ stats)
 {
-    const int32_t nbc = min(max(info[0], 0), K.n);
-    const int n = K.nsub;
-    for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < nbc; i += gridDim.x * blockDim.x) {
-        const int32_t key = min(max(list[i], 0), K.ncell - 1);
-        const int32_t cx = key % K.nc0, cy = (key / K.nc0) % K.nc1, cz = key / (K.nc0 * K.nc1);
-        const int32_t x0 = max(cx - n, 0), x1 = min(cx + n, K.nc0 - 1);
-        int32_t total = 0;
-        for (int dz = -n; dz <= n; ++dz)
-            for (int dy = -n; dy <= n; ++dy) {
-                const int32_t y = cy + dy, z = cz + dz;
-                if (y < 0 || y >= K.nc1 || z < 0 || z >= K.nc2) continue;
-                const int32_t k0 = K.ncell + x0 + K.nc0 * (y + K.nc1 * z);
-                total += start[k0 + (x1 - x0 + 1)] - start[k0];
-            }
-        if (total > 0) {
-            active[atomicAdd(nactive, 1)] = key;
-        } else if (ace) {
-            const int32_t b = min(max(start[key], 0), K.n), e = min(max(start[key + 1], b), K.n);
-            for (int32_t a = b; a < e; ++a) {
-                ace[a] = make_float4(0.f, 0.f, 0.f, 0.f);
-                visc[a] = 0.f;
-                if (stats) { stats[2 * a] = 0; stats[2 * a + 1] = 0; }
+    const int32_t stride = gridDim.x * blockDim.x;
+    const int32_t gid = blockIdx.x * blockDim.x + threadIdx.x;
+    if (ace) {
+        // slots [0, start[ncell]) hold the boundary particles inside the grid,
+        // the last info[2] slots the excluded particles
+        const int32_t nbs = min(max(start[K.ncell], 0), K.n);
+        const int32_t nex = min(max(info[2], 0), K.n - nbs);
+        for (int32_t i = gid; i < nbs + nex; i += stride) {
+            const int32_t a = i < nbs ? i : K.n - nex + (i - nbs);
+            ace[a] = make_float4(0.f, 0.f, 0.f, 0.f);
+            visc[a] = 0.f;
+            if (stats) {
+                stats[2 * a] = 0;
+                stats[2 * a + 1] = 0;
             }
         }
     }
-    if (ace) {  // excluded particles (the tail of the sorted state) get zero outputs
-        const int32_t nex = min(max(info[2], 0), K.n);
-        for (int32_t i = K.n - nex + blockIdx.x * blockDim.x + threadIdx.x; i < K.n;
-             i += gridDim.x * blockDim.x) {
-            ace[i] = make_float4(0.f, 0.f, 0.f, 0.f);
-            visc[i] = 0.f;
-            if (stats) { stats[2 * i] = 0; stats[2 * i + 1] = 0; }
-        }
+    const int32_t nbc = min(max(info[0], 0), K.n);
+    for (int32_t i = gid; i < nbc; i += stride) {
+        const int32_t key = min(max(list[i], 0), K.ncell - 1);
+        const int32_t total = K.nsub == 1 ? fluid_in_reach<1>(K, start, key)
+                                          : fluid_in_reach<2>(K, start, key);
+        if (total > 0) active[atomicAdd(nactive, 1)] = key;
     }
 }
 
