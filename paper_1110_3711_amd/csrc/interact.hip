@@ -12,8 +12,9 @@
 //   * the (2n+1)^2 X-runs of the stencil (Section 4.4: three consecutive
 //     cells along X are one contiguous range of the sorted arrays) are staged
 //     into LDS in the frame of the target cell: each candidate's offset gets
-//     (k_b - k_a) * cell added once, in FP32 (exact for |k_b - k_a| <= 2),
-//     and the staged candidates are ordered by 32 bins of their x, so that a
+//     (k_b - k_a) * cell added once, in FP32 (the shift is exact for
+//     |k_b - k_a| <= 2, the sum is rounded once), and the staged candidates
+//     are ordered by 32 bins of their x, so that a
 //     target scans only the window of bins within 2h of its own x;
 //   * one wavefront per target: 64 candidates per step are tested for
 //     r^2 < (2h)^2, survivors are compacted with a ballot into a per-wave ring
