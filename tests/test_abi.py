@@ -40,6 +40,17 @@ def test_library_exports_every_declared_symbol(lib):
     assert lib.sph_abi_version() == 3
 
 
+def test_library_resolves_every_symbol_at_load():
+    """Loading with immediate binding fails on any undefined symbol (for
+    instance a kernel whose host stub was not emitted), which lazy binding
+    would only report at the first launch."""
+    import ctypes
+
+    from paper_1110_3711_amd import sph
+
+    ctypes.CDLL(sph.LIB_PATH, mode=os.RTLD_NOW | os.RTLD_LOCAL)
+
+
 def _grid():
     from paper_1110_3711_amd import sph
 
