@@ -11,7 +11,7 @@
 import numpy as np
 import pytest
 
-from _helpers import grid_tuple, oracle_view, rel_l2
+from _helpers import compress, grid_tuple, oracle_view, rel_l2
 from sph_inputs import dam_break, named_case
 
 pytestmark = pytest.mark.gpu
@@ -30,14 +30,18 @@ def _oracle_state(ora, lay, sim):
     return oracle_view(ora, lay.x, lay.v, lay.rho, lay.phys.rho0, grid_tuple(sim), lay.lo, lay.hi)
 
 
-@pytest.mark.parametrize("which", ["small", "dam_break_8k"])
+@pytest.mark.parametrize("which", ["small", "dam_break_8k", "compressed"])
 def test_interact_backward_matches_oracle(ora, which):
     import torch
 
     from paper_1110_3711_amd import sph
 
-    lay = _case() if which == "small" else dam_break(0.01, 11103711 + 1, vel_sigma=0.2,
-                                                     vel_seed=9)
+    if which == "small":
+        lay = _case()
+    elif which == "compressed":  # stencils over several adjoint staging tiles
+        lay = compress(_case(dp=0.01), 0.5)
+    else:
+        lay = dam_break(0.01, 11103711 + 1, vel_sigma=0.2, vel_seed=9)
     print(f"interact_backward {which} n={lay.n}", flush=True)
     sim = sph.Simulation(lay, nsub=1)
     sim.build_cells()

@@ -9,7 +9,7 @@
 import numpy as np
 import pytest
 
-from _helpers import grid_tuple, oracle_view, rel_l2
+from _helpers import compress, grid_tuple, oracle_view, rel_l2
 from sph_inputs import blob, dam_break, named_case
 
 pytestmark = pytest.mark.gpu
@@ -92,6 +92,20 @@ def test_forces_blob_with_excluded(ora):
     lay.x[:50, 0] = lay.hi[0] + 1.0  # outside the domain: excluded
     print("interact forces blob", flush=True)
     sim, _ = _run(lay, 1)
+    _compare_forces(ora, lay, sim)
+
+
+def test_forces_compressed_several_tiles(ora):
+    # the 1,728-fluid dam break with positions pulled together by 0.5 (8x the
+    # lattice density): the stencils hold some 4,000 candidates (two or three
+    # staging tiles) and boundary cells hundreds of targets, beyond the ones
+    # staged in LDS
+    lay = compress(dam_break(0.01, 7, fluid=(0.12, 0.12, 0.12), tank=(0.2, 0.14, 0.14),
+                             vel_sigma=0.2, vel_seed=5), 0.5)
+    print(f"interact forces compressed dam break n={lay.n}", flush=True)
+    sim, _ = _run(lay, 1)
+    cells = sim.start.cpu().numpy()
+    assert np.diff(cells[: sim.ncell + 1]).max() > 128  # a boundary cell beyond the staged targets
     _compare_forces(ora, lay, sim)
 
 
