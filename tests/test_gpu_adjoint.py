@@ -30,7 +30,7 @@ def _oracle_state(ora, lay, sim):
     return oracle_view(ora, lay.x, lay.v, lay.rho, lay.phys.rho0, grid_tuple(sim), lay.lo, lay.hi)
 
 
-@pytest.mark.parametrize("which", ["small", "dam_break_8k", "compressed"])
+@pytest.mark.parametrize("which", ["small", "dam_break_8k", "dam_break_8k_nsub2", "compressed"])
 def test_interact_backward_matches_oracle(ora, which):
     import torch
 
@@ -43,7 +43,7 @@ def test_interact_backward_matches_oracle(ora, which):
     else:
         lay = dam_break(0.01, 11103711 + 1, vel_sigma=0.2, vel_seed=9)
     print(f"interact_backward {which} n={lay.n}", flush=True)
-    sim = sph.Simulation(lay, nsub=1)
+    sim = sph.Simulation(lay, nsub=2 if which.endswith("nsub2") else 1)
     sim.build_cells()
     rng = np.random.default_rng(21)
     w = rng.normal(size=(lay.n, 4))

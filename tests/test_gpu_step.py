@@ -27,8 +27,8 @@ def _oracle_state(ora, lay, sim, vprev=None, rhoprev=None):
     return S
 
 
-@pytest.mark.parametrize("step_index", [0, 5])
-def test_one_step_matches_oracle(ora, step_index):
+@pytest.mark.parametrize("step_index,nsub", [(0, 1), (5, 1), (0, 2)])
+def test_one_step_matches_oracle(ora, step_index, nsub):
     import torch
 
     from paper_1110_3711_amd import sph
@@ -38,8 +38,8 @@ def test_one_step_matches_oracle(ora, step_index):
     vprev = lay.v + rng.normal(0, 0.01, lay.v.shape)
     vprev[: lay.nb] = 0
     rhoprev = lay.rho + rng.normal(0, 0.05, lay.n)
-    print(f"step parity step={step_index}", flush=True)
-    sim = sph.Simulation(lay, nsub=1)
+    print(f"step parity step={step_index} nsub={nsub}", flush=True)
+    sim = sph.Simulation(lay, nsub=nsub)
     sim.upload_prev(vprev, rhoprev)
     sim.step_index = step_index
     sim.step()
