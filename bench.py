@@ -32,8 +32,11 @@ sys.path.insert(0, ROOT)
 
 METRIC = "pair interactions/s + steps/s, 1M-particle dam break FP32; adjoint/forward time"
 # Algorithmic FP32 operations per directed pair (FMA = 2), counted from the
-# pair arithmetic of the method (kernel gradient, continuity, Monaghan term,
-# Tait pressure terms, momentum accumulation); see the design notes.
+# pair arithmetic of the method: a fluid target costs r and r^2 8, sqrt 1,
+# kernel gradient factor 5, v_ab and v.r 8, continuity 2, mu 4, max |mu| 1,
+# rho_b and c_b 5, Monaghan term 6, pressure terms 2, coefficient 1,
+# momentum 6 (49); a boundary target only the distance, kernel factor, v.r
+# and continuity terms (24).
 FLOP_FLUID_PAIR = 49
 FLOP_BOUND_PAIR = 24
 # the cubic spline's gradient factor costs one operation more than the
@@ -52,7 +55,7 @@ def _kernel_source_hash():
 
 
 def _traffic_record():
-    """HBM bytes per launch of the fluid pair kernel from the committed
+    """HBM bytes per launch of the fused pair kernel from the committed
     rocprofv3 counter summary, if it was taken on the current kernel source."""
     p = os.path.join(ROOT, "profiles", "interact_dam_break_1m_traffic.json")
     if not os.path.exists(p):

@@ -16,7 +16,8 @@
  *   - Table 1 formulation: Verlet time integration, variable time step,
  *     artificial viscosity, Tait equation of state, dynamic boundaries.  The
  *     paper defers the equations to its ref. [11]; the standard forms of the
- *     cited schemes are used and every reading is listed in the design notes.
+ *     cited schemes are used, each written out above the function that
+ *     computes it.
  *   - Kernel: Wendland quintic (default) or the paper's cubic spline.
  *   - Optional tensile correction (the per-particle "tensil" of Table 3,
  *     following the paper's ref. [34]); off unless tensile_dp > 0.
