@@ -32,9 +32,13 @@ SEED_BASE = 11103711
 
 @dataclass(frozen=True)
 class Physics:
-    """Constants of one case (Table 1 formulation; see the readings in the docs).
+    """Constants of one case (Table 1 formulation).
 
-    ``h`` is the smoothing length; the kernel support is ``2h``.
+    ``h`` is the smoothing length, 1.2 sqrt(3) dp; the kernel support is ``2h``.
+    ``c0`` = 10 sqrt(g H) for the column height H; ``eta2`` = 0.01 h^2 (the
+    regulariser of the Monaghan term); ``mass`` = rho0 dp^3; ``cfl`` = 0.2.
+    Corrective Verlet step every ``verlet_ns`` steps; ``bound_floor`` keeps
+    boundary densities at or above rho0.
     ``kernel`` 0 = Wendland quintic, 1 = cubic spline.
     ``tensile_dp`` > 0 switches the tensile correction on, with that spacing
     in f = W(r)/W(dp); 0 = off.
