@@ -4,6 +4,8 @@ seeded 65,536-target subset with full neighbourhoods on the same encoded
 state.  Seeded velocities (0.05 m/s) exercise the continuity and viscous
 terms as well as the pressure term."""
 
+import dataclasses
+
 import numpy as np
 import pytest
 
@@ -54,6 +56,22 @@ def _grid(lay, nsub):
 def test_bench_layout_subset_parity(ora):
     lay = dam_break(0.002, SEED_BASE + 2, vel_sigma=0.05, vel_seed=SEED_BASE + 20, name="dam_break_1m+v")
     print("large: 1.65M-particle dam break", flush=True)
+    e = _subset_parity(ora, lay, 1)
+    assert max(e) <= 1e-4
+
+
+def test_bench_layout_subset_parity_cubic_tensile(ora):
+    """The same layout with the cubic spline (alpha = 0.25) and the tensile
+    correction, as `bench.py --kernel cubic --tensile` runs it; densities are
+    perturbed around rho0 so that both signs of the pressure (both branches
+    of the correction) occur."""
+    lay = dam_break(0.002, SEED_BASE + 2, vel_sigma=0.05, vel_seed=SEED_BASE + 20, kernel=1,
+                    name="dam_break_1m+v cubic tensile")
+    lay.phys = dataclasses.replace(lay.phys, alpha=0.25, tensile_dp=lay.phys.dp)
+    rng = np.random.default_rng(SEED_BASE + 21)
+    lay.rho = lay.rho + rng.normal(0.0, 3.0, lay.n)
+    lay.rho[: lay.nb] = np.abs(lay.rho[: lay.nb] - lay.phys.rho0) + lay.phys.rho0
+    print("large: 1.65M-particle dam break, cubic spline + tensile correction", flush=True)
     e = _subset_parity(ora, lay, 1)
     assert max(e) <= 1e-4
 
