@@ -148,6 +148,8 @@ def main():
                     help="smoothing kernel (cubic: the Table 1 spline, with alpha = 0.25)")
     ap.add_argument("--tensile", action="store_true",
                     help="tensile correction on (spacing = the layout's dp)")
+    ap.add_argument("--range-table", action="store_true",
+                    help="precomputed interaction ranges per cell (Section 4.4, optimisation D)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=12.0)
     ap.add_argument("--adjoint-config", default="dam_break_64k",
@@ -184,7 +186,7 @@ def main():
 
     lay = variant(named_case(args.config))
     torch.cuda.reset_peak_memory_stats()
-    sim = sph.Simulation(lay, nsub=args.nsub)
+    sim = sph.Simulation(lay, nsub=args.nsub, ranges=args.range_table)
     stream = torch.cuda.current_stream()
 
     # warmup (also brings the dam-break state past its first steps)
@@ -232,7 +234,7 @@ def main():
     # the committed counter record holds the default kernel (Wendland, no
     # tensile correction) on the 1M-particle layout only
     default_path = (args.config == "dam_break_1m" and args.kernel == "wendland" and
-                    not args.tensile and args.nsub == 1)
+                    not args.tensile and args.nsub == 1 and not args.range_table)
     traffic = _traffic_record() if default_path else None
     achieved = flop_launch / (pi_ms.mean() / 1e3)
     roof = {
@@ -271,6 +273,7 @@ def main():
             "boundary": lay.nb,
             "nsub": args.nsub,
             "cells": sim.ncell,
+            "range_table": bool(args.range_table),
             "kernel": ("cubic spline, alpha = 0.25" if args.kernel == "cubic" else
                        "Wendland quintic") + ", h = 1.2 sqrt(3) dp, support 2h" +
                       (", tensile correction" if args.tensile else ""),

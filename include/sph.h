@@ -53,7 +53,7 @@
 extern "C" {
 #endif
 
-#define SPH_ABI_VERSION 3 /* 2: two-entry npairs; 3: sph_params.tensile_dp */
+#define SPH_ABI_VERSION 4 /* 2: two-entry npairs; 3: sph_params.tensile_dp; 4: sph_cells.ranges */
 #define SPH_API __attribute__((visibility("default")))
 #define SPH_EXCLUDED INT32_MAX /* cell index of a particle outside the domain */
 
@@ -127,13 +127,28 @@ typedef struct {
 
 /* Output of the neighbour list (CellBeginEnd of Section 4.1, stored as one
  * prefix array).  Keys: boundary cell k -> k, fluid cell k -> ncell + k,
- * excluded -> 2 ncell. */
+ * excluded -> 2 ncell.
+ *
+ * ranges (optional, NULL = not used): the interaction ranges of every cell
+ * precomputed by sph_build_cells (Section 4.4, optimisation D: the 27 cells,
+ * 125 with nsub = 2, of a stencil read as (2 nsub + 1)^2 X-runs of
+ * consecutive cells, each one range of sorted slots).  Layout: int32
+ * [ncell][2][(2 nsub + 1)^2][2]: for cell c, particle type t (0 boundary,
+ * 1 fluid) and run r = (dy + nsub) + (2 nsub + 1)(dz + nsub), the pair
+ * (first slot, end slot) of the type-t particles in the cells
+ * (max(cx - nsub, 0) .. min(cx + nsub, nc0 - 1), cy + dy, cz + dz); (0, 0)
+ * for a run outside the grid.  144 bytes per cell with nsub = 1, 400 with
+ * nsub = 2: sph_ranges_bytes().  sph_build_cells writes the rows of the cells
+ * that hold particles (other rows are left as they are); sph_interact and
+ * sph_interact_backward then read each target cell's runs from its row
+ * instead of deriving them from start[], with bitwise identical results. */
 typedef struct {
-    int32_t *start; /* [2*ncell + 2]: start[key] = first sorted slot with that key or a
-                       larger one; particles of key k are [start[k], start[k+1])         */
-    int32_t *list;  /* [n] non-empty keys in ascending order (boundary cells first)      */
-    int32_t *info;  /* [4] (device): non-empty boundary cells, non-empty fluid cells,
-                       excluded particles, reserved                                     */
+    int32_t *start;  /* [2*ncell + 2]: start[key] = first sorted slot with that key or a
+                        larger one; particles of key k are [start[k], start[k+1])         */
+    int32_t *list;   /* [n] non-empty keys in ascending order (boundary cells first)      */
+    int32_t *info;   /* [4] (device): non-empty boundary cells, non-empty fluid cells,
+                        excluded particles, reserved                                     */
+    int32_t *ranges; /* optional [sph_ranges_bytes(g) / 4], see above; NULL: not used    */
 } sph_cells;
 
 /* Adjoint buffers (device, [4n] each, in the slot order of one state).  The
@@ -149,6 +164,10 @@ typedef struct {
 /* Size in bytes of the workspace needed by all calls for n particles on
  * grid g; 0 if the arguments are invalid. */
 SPH_API size_t sph_workspace_bytes(const sph_grid *g, int32_t n);
+
+/* Size in bytes of the optional interaction-range table of grid g
+ * (sph_cells.ranges): ncell * 2 * (2 nsub + 1)^2 * 8; 0 if g is invalid. */
+SPH_API size_t sph_ranges_bytes(const sph_grid *g);
 
 /* ABI version of the loaded library (SPH_ABI_VERSION). */
 SPH_API int32_t sph_abi_version(void);

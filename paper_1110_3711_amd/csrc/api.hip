@@ -71,6 +71,13 @@ extern "C" {
 
 int32_t sph_abi_version(void) { return SPH_ABI_VERSION; }
 
+size_t sph_ranges_bytes(const sph_grid *g)
+{
+    if (!grid_ok(g)) return 0;
+    const size_t side = 2 * (size_t)g->nsub + 1;
+    return (size_t)ncell_of(g) * 2 * side * side * 2 * sizeof(int32_t);
+}
+
 size_t sph_workspace_bytes(const sph_grid *g, int32_t n)
 {
     if (!grid_ok(g) || n < 0) return 0;

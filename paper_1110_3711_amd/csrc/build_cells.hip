@@ -1,11 +1,14 @@
 // build_cells.hip -- neighbour-list stage (Section 4.1): cell keys, a stable
 // LSD radix sort of (key, slot), the cell start array, the list of non-empty
-// keys and the reorder of every particle array into cell order.
+// keys, the reorder of every particle array into cell order and, on request,
+// the interaction ranges of every occupied cell (Section 4.4, optimisation D).
 //
 // Keys: boundary cell k -> k, fluid cell k -> ncell + k, excluded -> 2 ncell,
 // so the sorted order is boundary cells, then fluid cells, then excluded
 // particles, each cell contiguous and cells X fastest (the X-run property
 // used by the interaction stencil, Section 4.4).
+#include <algorithm>
+
 #include "sph_internal.h"
 
 namespace sph {
@@ -295,6 +298,40 @@ __global__ void k_emit_ranges(int64_t nkeys, int32_t n, int32_t ncell,
     }
 }
 
+// Interaction ranges (Section 4.4, optimisation D): for every cell with
+// particles, the slot range [first, end) of each X-run of its stencil, per
+// particle type.  Rows are indexed by cell, 2 (2n+1)^2 (first, end) pairs
+// each; a cell that holds both boundary and fluid particles is written from
+// its fluid key only, so every row has one writer.
+__global__ void k_range_rows(int32_t ncell, int32_t nc0, int32_t nc1, int32_t nc2, int32_t nsub,
+                             const int32_t *__restrict__ start, const int32_t *__restrict__ list,
+                             const int32_t *__restrict__ info, int2 *__restrict__ rows)
+{
+    const int side = 2 * nsub + 1;
+    const int per = 2 * side * side;
+    const int64_t nlist = (int64_t)max(info[0], 0) + max(info[1], 0);
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < nlist * per; t += stride) {
+        const int64_t p = t / per;
+        const int r = (int)(t - p * per);
+        const int32_t key = list[p];
+        const bool fluid = key >= ncell;
+        const int32_t c = fluid ? key - ncell : key;
+        if (!fluid && start[ncell + c + 1] > start[ncell + c]) continue;
+        const int32_t cx = c % nc0, cy = (c / nc0) % nc1, cz = c / (nc0 * nc1);
+        const int type = r / (side * side);
+        const int rr = r - type * side * side;
+        const int32_t y = cy + rr % side - nsub, z = cz + rr / side - nsub;
+        int2 v = make_int2(0, 0);
+        if (y >= 0 && y < nc1 && z >= 0 && z < nc2) {
+            const int32_t x0 = max(cx - nsub, 0), x1 = min(cx + nsub, nc0 - 1);
+            const int32_t k0 = (type ? ncell : 0) + x0 + nc0 * (y + nc1 * z);
+            v = make_int2(start[k0], start[k0 + (x1 - x0 + 1)]);
+        }
+        rows[(int64_t)c * per + r] = v;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // gather into sorted order
 
@@ -360,6 +397,15 @@ hipError_t launch_build_cells(const sph_grid *g, const sph_state *src, sph_state
     if (e != hipSuccess) return e;
     k_emit_ranges<<<(unsigned)((lenks + threads - 1) / threads), threads, 0, s>>>(
         nkeys, n, ncell, w.keyscan, cells->start, cells->list, cells->info);
+    if (cells->ranges && n > 0) {
+        // at most n listed keys, 2 (2n+1)^2 runs each
+        const int side = 2 * g->nsub + 1;
+        const int64_t work = (int64_t)n * 2 * side * side;
+        const unsigned blocks = (unsigned)std::min<int64_t>((work + threads - 1) / threads, 4096);
+        k_range_rows<<<blocks, threads, 0, s>>>(ncell, g->nc[0], g->nc[1], g->nc[2], g->nsub,
+                                                cells->start, cells->list, cells->info,
+                                                (int2 *)cells->ranges);
+    }
     // 4. gather
     if (n > 0)
         k_gather<<<(n + threads - 1) / threads, threads, 0, s>>>(

@@ -44,7 +44,6 @@ constexpr int kWaves = kThreads / kWave;
 constexpr int kTile = 2048;          // candidates staged per pass (multiple of 64)
 constexpr int kRing = 128;           // per-wave ring of compacted candidates
 constexpr int kMaxRuns = 2 * 25;     // types x (2n+1)^2, n <= 2
-constexpr int kMaxRunCells = 5;      // 2n+1
 constexpr float kFar = 1.0e30f;      // padding position: never within the support
 constexpr int kXcds = 8;             // MI355X: workgroups are dealt to 8 XCDs round robin
 constexpr int kBinBits = 5;          // staged candidates are ordered by 32 bins of x
@@ -54,10 +53,9 @@ struct RunTable {
     int32_t nruns;
     int32_t total;                          // candidates over all runs
     int32_t vstart[kMaxRuns + 1];           // prefix of run lengths
-    int32_t s[kMaxRuns][kMaxRunCells + 1];  // slot starts of the run's cells, last = end
-    int32_t ncx[kMaxRuns];
-    int32_t dx0[kMaxRuns];                  // x0 - cx
+    int32_t s[kMaxRuns];                    // first slot of the run
     float sy[kMaxRuns], sz[kMaxRuns];       // dy * cell, dz * cell
+    int32_t cb[kMaxRuns];                   // linear index of cell (cx, cy + dy, cz + dz)
     int32_t self_run;                       // run holding the target cell's own fluid particles
 };
 
@@ -209,11 +207,15 @@ __device__ inline uint32_t lds_addr(const void *p)
 // ---------------------------------------------------------------------------
 // stencil runs of a target cell
 
-// Build the run table of target cell (cx, cy, cz).  FLUID: candidates are
-// boundary and fluid particles; otherwise fluid only.
+// Build the run table of target cell c = (cx, cy, cz).  FLUID: candidates
+// are boundary and fluid particles; otherwise fluid only.  With precomputed
+// interaction ranges (rows != nullptr, Section 4.4 optimisation D) each run
+// is read from the cell's row, otherwise from the starts of its first cell
+// and of the cell after its last one.
 template <bool FLUID>
-__device__ void build_runs(const PairConsts &K, const int32_t *__restrict__ start, int32_t cx,
-                           int32_t cy, int32_t cz, RunTable &R)
+__device__ void build_runs(const PairConsts &K, const int32_t *__restrict__ start,
+                           const int2 *__restrict__ rows, int32_t c, int32_t cx, int32_t cy,
+                           int32_t cz, RunTable &R)
 {
     const int n = K.nsub;
     const int side = 2 * n + 1;
@@ -229,24 +231,19 @@ __device__ void build_runs(const PairConsts &K, const int32_t *__restrict__ star
         const int dy = rr % side - n, dz = rr / side - n;
         const int32_t y = cy + dy, z = cz + dz;
         const bool ok = y >= 0 && y < K.nc1 && z >= 0 && z < K.nc2;
-        // key of the run's first cell; key0 + ncx <= 2 ncell, and 0 + ncx
-        // <= ncell for a run outside the grid, so the loads below are in
-        // bounds unconditionally and are all issued before the first use
-        int32_t key0 = 0;
-        if (ok) key0 = (type ? K.ncell : 0) + x0 + K.nc0 * (y + K.nc1 * z);
-        int32_t sv[kMaxRunCells + 1];
-#pragma unroll
-        for (int i = 0; i <= kMaxRunCells; ++i) sv[i] = start[key0 + min(i, ncx)];
-        int32_t s0 = 0, se = 0;
-#pragma unroll
-        for (int i = 0; i <= kMaxRunCells; ++i) {
-            const int32_t v = ok ? sv[i] : 0;
-            R.s[r][i] = v;
-            if (i == 0) s0 = v;
-            if (i == ncx) se = v;
+        int2 be;
+        if (rows) {
+            // row of cell c: (first, end) of type `type`, run rr
+            be = rows[(int64_t)c * (2 * side * side) + type * side * side + rr];
+        } else {
+            // key of the run's first cell; key0 + ncx <= 2 ncell, and 0 + ncx
+            // <= ncell for a run outside the grid, so both loads are in bounds
+            const int32_t key0 = ok ? (type ? K.ncell : 0) + x0 + K.nc0 * (y + K.nc1 * z) : 0;
+            be = make_int2(start[key0], start[key0 + ncx]);
         }
-        R.ncx[r] = ok ? ncx : 0;
-        R.dx0[r] = x0 - cx;
+        const int32_t s0 = ok ? be.x : 0, se = ok ? be.y : 0;
+        R.s[r] = s0;
+        R.cb[r] = ok ? cx + K.nc0 * (y + K.nc1 * z) : 0;
         R.sy[r] = (float)dy * K.cellf;
         R.sz[r] = (float)dz * K.cellf;
         if (type == 1 && dy == 0 && dz == 0) R.self_run = r;
@@ -279,6 +276,8 @@ enum Kind { kFwdFluid = 0, kFwdBound = 1, kBwdFluid = 2, kBwdBound = 3, kFwdAll 
 struct PairArgs {
     const int32_t *start, *items, *counts;
     const int32_t *items2, *counts2;  // fused launches: active boundary cells, their count
+    const int2 *ranges;       // precomputed interaction ranges of the cells, or nullptr
+    const int32_t *cell;      // cell of each slot (read with ranges only)
     const float4 *pos, *velrho;
     const int32_t *ids;
     float4 *ace;        // forward: out (a, drho/dt); backward: in (abar, Dbar)
@@ -365,7 +364,7 @@ __device__ __forceinline__ void pair_item(const PairConsts &K, const PairArgs &A
     const int32_t tbeg = __builtin_amdgcn_readfirstlane(min(max(A.start[key], 0), K.n));
     const int32_t tend = __builtin_amdgcn_readfirstlane(min(max(A.start[key + 1], tbeg), K.n));
 
-    build_runs<FLUID>(K, A.start, cx, cy, cz, R);
+    build_runs<FLUID>(K, A.start, A.ranges, c, cx, cy, cz, R);
     const int32_t total = __builtin_amdgcn_readfirstlane(R.total);
     const int nr = __builtin_amdgcn_readfirstlane(R.nruns);
     const int nbruns = FLUID ? nr / 2 : 0;  // runs [0, nbruns) hold boundary particles
@@ -384,14 +383,13 @@ __device__ __forceinline__ void pair_item(const PairConsts &K, const PairArgs &A
                 if (R.vstart[mid] <= v) lo = mid;
                 else hi = mid;
             }
-            j = min(max(R.s[lo][0] + (v - R.vstart[lo]), 0), K.n - 1);
+            j = min(max(R.s[lo] + (v - R.vstart[lo]), 0), K.n - 1);
             run = lo;
         };
-        // frame shift (k_b - k_a) cell along x, exact
+        // frame shift (k_b - k_a) cell along x, exact: the candidate's cell and
+        // the run's centre cell differ by k_b - k_a in x
         auto shift_x = [&](int32_t j, int run) {
-            int ci = 0;
-            for (int i = 1; i < R.ncx[run]; ++i) ci += R.s[run][i] <= j ? 1 : 0;
-            return (float)(R.dx0[run] + ci) * K.cellf;
+            return (float)(A.cell[j] - R.cb[run]) * K.cellf;
         };
         // rank among the equal x-bins of this wave (stable in lane order)
         auto rank_round = [&](int u, int bin) {
@@ -487,7 +485,7 @@ __device__ __forceinline__ void pair_item(const PairConsts &K, const PairArgs &A
 
         // ---- one wavefront per target
         const int32_t selfbase =
-            FLUID ? __builtin_amdgcn_readfirstlane(R.vstart[R.self_run] - R.s[R.self_run][0]) - tb
+            FLUID ? __builtin_amdgcn_readfirstlane(R.vstart[R.self_run] - R.s[R.self_run]) - tb
                   : 0;
         for (int32_t a = tbeg + wave; a < tend; a += kWaves) {
             const int32_t self_v = FLUID ? selfbase + a : -1;  // staging index of a
@@ -768,12 +766,12 @@ __device__ __forceinline__ void pair_item(const PairConsts &K, const PairArgs &A
 
 // Four waves per SIMD (two workgroups per CU) is what the LDS allows, and the
 // kernel needs them to hide its LDS and memory latency; at 129+ VGPRs only
-// three fit (about 1.6x the time).  The tensile adjoint is held to 128 VGPRs
+// three fit (about 1.6x the time).  The tensile kinds are held to 128 VGPRs
 // (without spills); the other instantiations fit by themselves, and the
 // constraint would cost them 1-2% of scheduling freedom.
 template <int KIND, bool STATS, int KER, bool TENS>
 __global__ __launch_bounds__(kThreads)
-__attribute__((amdgpu_waves_per_eu(KindTraits<KIND>::bwd && TENS ? 4 : 1, 4))) void k_interact(
+__attribute__((amdgpu_waves_per_eu(TENS ? 4 : 1, 4))) void k_interact(
     PairConsts K, PairArgs A)
 {
     using T = KindTraits<KIND>;
@@ -1053,6 +1051,8 @@ static PairArgs base_args(const sph_state *st, const sph_cells *cells)
     A.start = cells->start;
     A.items = cells->list;
     A.counts = cells->info;
+    A.ranges = (const int2 *)cells->ranges;
+    A.cell = st->cell;
     A.pos = (const float4 *)st->pos;
     A.velrho = (const float4 *)st->velrho;
     A.ids = st->id;

@@ -21,9 +21,9 @@ SPH_DEV_OUT_OF_GRID, SPH_DEV_NONFINITE = 1, 2
 SPH_FIXED_DT, SPH_ADJOINT = 1, 2
 SPH_PI_FLUID, SPH_PI_BOUNDARY, SPH_PI_ALL = 1, 2, 3
 SPH_EXCLUDED = 2**31 - 1
-ABI_VERSION = 3
+ABI_VERSION = 4
 
-EXPORTS = ["sph_workspace_bytes", "sph_abi_version", "sph_encode", "sph_decode",
+EXPORTS = ["sph_workspace_bytes", "sph_ranges_bytes", "sph_abi_version", "sph_encode", "sph_decode",
            "sph_build_cells", "sph_interact", "sph_step", "sph_interact_backward",
            "sph_build_cells_backward"]
 
@@ -47,7 +47,8 @@ class State(C.Structure):
 
 
 class Cells(C.Structure):
-    _fields_ = [("start", C.c_void_p), ("list", C.c_void_p), ("info", C.c_void_p)]
+    _fields_ = [("start", C.c_void_p), ("list", C.c_void_p), ("info", C.c_void_p),
+                ("ranges", C.c_void_p)]
 
 
 class Adjoint(C.Structure):
@@ -75,6 +76,8 @@ def load(path: str = LIB_PATH):
     P = C.POINTER
     L.sph_workspace_bytes.argtypes = [P(Grid), C.c_int32]
     L.sph_workspace_bytes.restype = sz
+    L.sph_ranges_bytes.argtypes = [P(Grid)]
+    L.sph_ranges_bytes.restype = sz
     L.sph_abi_version.argtypes = []
     L.sph_abi_version.restype = C.c_int32
     L.sph_encode.argtypes = [P(Grid), P(Params), vp, vp, vp, P(State), vp, vp]
@@ -138,6 +141,10 @@ def _stream(stream=None):
 
 def sph_workspace_bytes(grid: Grid, n: int) -> int:
     return load().sph_workspace_bytes(C.byref(grid), int(n))
+
+
+def sph_ranges_bytes(grid: Grid) -> int:
+    return load().sph_ranges_bytes(C.byref(grid))
 
 
 def sph_encode(grid, params, x, v, rho, state, dev_status, stream=None):
@@ -288,7 +295,7 @@ class Simulation:
     the device.
     """
 
-    def __init__(self, layout, nsub: int = 1, device="cuda:0", grid=None):
+    def __init__(self, layout, nsub: int = 1, device="cuda:0", grid=None, ranges=False):
         import torch
 
         from sph_inputs import cell_grid
@@ -313,6 +320,11 @@ class Simulation:
         self.start = torch.empty(2 * self.ncell + 2, dtype=torch.int32, device=self.device)
         self.list = torch.empty(max(n, 1), dtype=torch.int32, device=self.device)
         self.info = torch.zeros(4, dtype=torch.int32, device=self.device)
+        # optional precomputed interaction ranges (144 B per cell with nsub = 1)
+        self.ranges = None
+        if ranges:
+            self.ranges = torch.zeros(sph_ranges_bytes(grid) // 4, dtype=torch.int32,
+                                      device=self.device)
         self.perm = torch.empty(max(n, 1), dtype=torch.int32, device=self.device)
         self.ace = torch.empty((max(n, 1), 4), dtype=torch.float32, device=self.device)
         self.visc = torch.empty(max(n, 1), dtype=torch.float32, device=self.device)
@@ -328,6 +340,7 @@ class Simulation:
             c = Cells()
             c.start, c.list, c.info = (self.start.data_ptr(), self.list.data_ptr(),
                                        self.info.data_ptr())
+            c.ranges = None if self.ranges is None else self.ranges.data_ptr()
             self._cells = c
         return self._cells
 

@@ -37,7 +37,7 @@ def test_library_exports_every_declared_symbol(lib):
     for name in _declared():
         assert hasattr(lib, name), name
     assert sorted(sph.EXPORTS) == _declared()
-    assert lib.sph_abi_version() == 3
+    assert lib.sph_abi_version() == 4
 
 
 def test_library_resolves_every_symbol_at_load():
@@ -68,6 +68,19 @@ def test_workspace_query(lib):
     small = sph.make_grid([0, 0, 0], [1, 1, 1], 0.01, [20, 20, 20], 1)  # does not cover
     assert sph.sph_workspace_bytes(small, 1000) == 0
     assert sph.sph_workspace_bytes(g, -1) == 0
+
+
+def test_range_table_size(lib):
+    """Interaction ranges (Section 4.4, optimisation D): 9 X-runs x 2 particle
+    types x (first, end) = 144 bytes per cell with cells of side 2h, 25 runs
+    (400 bytes) with cells of side h."""
+    from paper_1110_3711_amd import sph
+
+    assert sph.sph_ranges_bytes(_grid()) == 20 ** 3 * 144
+    g2 = sph.make_grid([0, 0, 0], [1, 1, 1], 0.025, [40, 40, 40], 2)
+    assert sph.sph_ranges_bytes(g2) == 40 ** 3 * 400
+    bad = sph.make_grid([0, 0, 0], [1, 1, 1], 0.05, [20, 20, 20], 3)
+    assert sph.sph_ranges_bytes(bad) == 0
 
 
 def test_validation_errors_before_any_device_work(lib):

@@ -102,3 +102,49 @@ def test_build_cells_empty_and_tiny(ora):
     print(f"build_cells tiny n={lay.n}", flush=True)
     sim = sph.Simulation(lay, nsub=2)
     _check(ora, lay, sim, lay.x, lay.v, lay.rho)
+
+
+def _expected_ranges(start, ncell, nc, nsub, cells):
+    """Interaction ranges (Section 4.4, optimisation D) written out from the
+    cell starts: per cell, type (boundary, fluid) and X-run (dy, dz), the
+    slots from the first particle of the run's first cell to the last of its
+    last cell; (0, 0) for runs outside the grid."""
+    side = 2 * nsub + 1
+    nc0, nc1, nc2 = nc
+    rows = np.zeros((len(cells), 2, side * side, 2), dtype=np.int64)
+    for i, c in enumerate(cells):
+        cx, cy, cz = c % nc0, (c // nc0) % nc1, c // (nc0 * nc1)
+        x0, x1 = max(cx - nsub, 0), min(cx + nsub, nc0 - 1)
+        for t in range(2):
+            for rr in range(side * side):
+                y, z = cy + rr % side - nsub, cz + rr // side - nsub
+                if 0 <= y < nc1 and 0 <= z < nc2:
+                    k0 = t * ncell + x0 + nc0 * (y + nc1 * z)
+                    rows[i, t, rr] = (start[k0], start[k0 + x1 - x0 + 1])
+    return rows
+
+
+@pytest.mark.parametrize("nsub", [1, 2])
+def test_range_table_8k(ora, nsub):
+    """The optional range table: rows of every cell with particles equal the
+    ranges written out from the expected cell starts; other rows are left as
+    they were."""
+    import torch
+
+    from paper_1110_3711_amd import sph
+
+    lay = dam_break(0.01, 11103711 + 1, vel_sigma=0.2, vel_seed=77)
+    print(f"build_cells range table nsub={nsub} n={lay.n}", flush=True)
+    sim = sph.Simulation(lay, nsub=nsub, ranges=True)
+    side = 2 * nsub + 1
+    assert sim.ranges.numel() == sim.ncell * 2 * side * side * 2
+    sim.ranges.fill_(-7)
+    _, start, uniq, _, _, _ = _expected(ora, lay, sim, lay.x, lay.v, lay.rho)
+    sim.build_cells()
+    torch.cuda.synchronize()
+    got = sim.ranges.cpu().numpy().reshape(sim.ncell, 2, side * side, 2)
+    cells = np.unique(uniq % sim.ncell)
+    want = _expected_ranges(start, sim.ncell, [int(c) for c in sim.grid.nc], nsub, cells)
+    assert np.array_equal(got[cells], want)
+    empty = np.setdiff1d(np.arange(sim.ncell), cells)
+    assert np.all(got[empty] == -7)

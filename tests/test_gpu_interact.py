@@ -109,6 +109,44 @@ def test_forces_compressed_several_tiles(ora):
     _compare_forces(ora, lay, sim)
 
 
+@pytest.mark.parametrize("which", ["dam_break_8k", "dam_break_8k_nsub2", "compressed"])
+def test_range_table_path_bitwise(ora, which):
+    """With the precomputed interaction ranges the pair kernels read each
+    cell's runs from its row: forces, visc, pair counts and the pair VJP are
+    bitwise those of the default path (and within the bar of the oracle)."""
+    import torch
+
+    from paper_1110_3711_amd import sph
+
+    if which == "compressed":
+        lay = compress(dam_break(0.01, 7, fluid=(0.12, 0.12, 0.12), tank=(0.2, 0.14, 0.14),
+                                 vel_sigma=0.2, vel_seed=5), 0.5)
+    else:
+        lay = dam_break(0.01, 11103711 + 1, vel_sigma=0.2, vel_seed=77)
+    nsub = 2 if which.endswith("nsub2") else 1
+    print(f"interact range table {which} n={lay.n}", flush=True)
+    out = []
+    for ranges in (False, True):
+        sim = sph.Simulation(lay, nsub=nsub, ranges=ranges)
+        sim.build_cells()
+        sim.npairs.zero_()
+        sim.interact()
+        rng = np.random.default_rng(21)
+        w = torch.as_tensor(rng.normal(size=(lay.n, 4)), dtype=torch.float32,
+                            device=sim.device)[sim.a.id.long()].contiguous()
+        xb = torch.zeros((lay.n, 4), dtype=torch.float32, device=sim.device)
+        vb = torch.zeros((lay.n, 4), dtype=torch.float32, device=sim.device)
+        ab = torch.zeros(1, dtype=torch.float64, device=sim.device)
+        sph.sph_interact_backward(sim.grid, sim.params, sim.a.c(), sim.cells(), w, xb, vb, ab,
+                                  sim.ws)
+        torch.cuda.synchronize()
+        out.append((sim, sim.ace.clone(), sim.visc.clone(), sim.npairs.clone(), xb, vb, ab))
+    (_, *a), (sim_rt, *b) = out
+    for u, v in zip(a, b):
+        assert torch.equal(u, v)
+    _compare_forces(ora, lay, sim_rt)
+
+
 def test_momentum_conservation_gpu(ora):
     # pair forces are antisymmetric; the FP32 sum of internal forces over a
     # free blob vanishes to FP32 rounding
