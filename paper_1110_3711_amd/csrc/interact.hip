@@ -544,7 +544,15 @@ __device__ __forceinline__ void pair_item(const PairConsts &K, const PairArgs &A
                 const float4 vb = lds_load4(sVb + off);
                 const float rx = pa.x - pb.x, ry = pa.y - pb.y, rz = pa.z - pb.z;
                 const float r2 = __builtin_fmaf(rz, rz, __builtin_fmaf(ry, ry, rx * rx));
-                const float r = __builtin_amdgcn_sqrtf(r2);
+                // the adjoint needs 1/r too: one reciprocal square root instead of
+                // a square root and a reciprocal (r = 0 only for the target itself)
+                float r, ir = 0.f;
+                if (BWD) {
+                    ir = __builtin_amdgcn_rsqf(r2);
+                    r = r2 > 0.f ? r2 * ir : 0.f;
+                } else {
+                    r = __builtin_amdgcn_sqrtf(r2);
+                }
                 // kernel gradient factor in units of gs: F = gs G (grad_a W = F r_ab)
                 float G, wq = 0.f, qq = 0.f;
                 if (KER == SPH_WENDLAND5) {
@@ -616,9 +624,8 @@ __device__ __forceinline__ void pair_item(const PairConsts &K, const PairArgs &A
                         // (dF/dr) / r; 0 for the self pair
                         float Fr;
                         if (KER == SPH_WENDLAND5) {
-                            Fr = K.kfr * wq * wq * __builtin_amdgcn_rcpf(r);
+                            Fr = K.kfr * wq * wq * ir;
                         } else {
-                            const float ir = __builtin_amdgcn_rcpf(r);
                             Fr = qq < 1.f ? K.kcr_in * ir
                                           : K.kcr_out * __builtin_fmaf(-qq, qq, 4.f) * (ir * ir * ir);
                         }
@@ -632,15 +639,17 @@ __device__ __forceinline__ void pair_item(const PairConsts &K, const PairArgs &A
                         if (TENS) sm = __builtin_fmaf(rab, f4, sm);
                         const float dpi_dmu = mu < 0.f ? K.kpi * cr : 0.f;
                         const float e1 = F * Q * dpi_dmu;
-                        const float e1h = e1 * K.h * invden;
-                        float e2 = __builtin_fmaf(-2.f * e1 * invden, mu, sm * Q * Fr);
+                        const float e1i = e1 * invden;
+                        const float e1h = e1i * K.h;
+                        float e2 = __builtin_fmaf(-2.f * e1i, mu, sm * Q * Fr);
                         // tensile: d(R_ab f^4)/dx_a = R_ab 4 f^3 (F / W(dp)) r_ab
                         if (TENS) e2 = __builtin_fmaf(4.f * rab * f3 * K.inv_wdp, F * F * Q, e2);
                         const float e3 = sm * F;
-                        s0 += __builtin_fmaf(c1, vx, c2 * rx) - __builtin_fmaf(e1h, vx, __builtin_fmaf(e2, rx, e3 * dax));
-                        s1 += __builtin_fmaf(c1, vy, c2 * ry) - __builtin_fmaf(e1h, vy, __builtin_fmaf(e2, ry, e3 * day));
-                        s2 += __builtin_fmaf(c1, vz, c2 * rz) - __builtin_fmaf(e1h, vz, __builtin_fmaf(e2, rz, e3 * daz));
-                        const float g = c1 - e1h;
+                        // c1 v + c2 r - (e1h v + e2 r + e3 da), grouped by vector
+                        const float g = c1 - e1h, hr = c2 - e2;
+                        s0 = __builtin_fmaf(g, vx, __builtin_fmaf(hr, rx, __builtin_fmaf(-e3, dax, s0)));
+                        s1 = __builtin_fmaf(g, vy, __builtin_fmaf(hr, ry, __builtin_fmaf(-e3, day, s1)));
+                        s2 = __builtin_fmaf(g, vz, __builtin_fmaf(hr, rz, __builtin_fmaf(-e3, daz, s2)));
                         s4 = __builtin_fmaf(g, rx, s4);
                         s5 = __builtin_fmaf(g, ry, s5);
                         s6 = __builtin_fmaf(g, rz, s6);
