@@ -70,6 +70,43 @@ def test_workspace_query(lib):
     assert sph.sph_workspace_bytes(g, -1) == 0
 
 
+def test_ctypes_structs_match_header(tmp_path):
+    """The binding's ctypes structures have the sizes and member offsets that a
+    C compiler gives the structs of include/sph.h."""
+    import shutil
+    import subprocess
+
+    from paper_1110_3711_amd import sph
+
+    gcc = shutil.which("gcc")
+    if gcc is None:
+        pytest.skip("no C compiler")
+    structs = {"sph_grid": sph.Grid, "sph_params": sph.Params, "sph_state": sph.State,
+               "sph_cells": sph.Cells, "sph_adjoint": sph.Adjoint}
+    lines = ["#include <stddef.h>", "#include <stdio.h>", '#include "sph.h"', "int main(void) {"]
+    for cname, cls in structs.items():
+        lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f, _ in cls._fields_:
+            lines.append(f'  printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    inc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
+    subprocess.run([gcc, "-D__HIP_PLATFORM_AMD__", "-I/opt/rocm/include", "-I" + inc, "-o",
+                    str(exe), str(src)], check=True, capture_output=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {}
+    for ln in out:
+        if ln:
+            cname, key, val = ln.split()
+            got[(cname, key)] = int(val)
+    for cname, cls in structs.items():
+        assert got[(cname, "size")] == C.sizeof(cls), cname
+        for f, _ in cls._fields_:
+            assert got[(cname, f)] == getattr(cls, f).offset, (cname, f)
+
+
 def test_range_table_size(lib):
     """Interaction ranges (Section 4.4, optimisation D): 9 X-runs x 2 particle
     types x (first, end) = 144 bytes per cell with cells of side 2h, 25 runs
