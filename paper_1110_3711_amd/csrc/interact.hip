@@ -277,7 +277,7 @@ struct PairArgs {
     const int32_t *start, *items, *counts;
     const int32_t *items2, *counts2;  // fused launches: active boundary cells, their count
     const int2 *ranges;       // precomputed interaction ranges of the cells, or nullptr
-    const int32_t *cell;      // cell of each slot (read with ranges only)
+    const int32_t *cell;      // cell of each slot (the frame shift of a staged candidate)
     const float4 *pos, *velrho;
     const int32_t *ids;
     float4 *ace;        // forward: out (a, drho/dt); backward: in (abar, Dbar)
