@@ -184,3 +184,26 @@ def test_product_path_has_no_cpu_fallback():
                 txt = open(os.path.join(dirpath, f)).read()
                 assert "import oracle" not in txt and "from oracle" not in txt, f
                 assert "sph_oracle" not in txt, f
+
+
+def test_c_driver_rejects_bad_input(tmp_path):
+    """The plain-C driver checks its input before it touches a device: usage,
+    a header with nb > n and a truncated file end with an error status."""
+    import struct
+    import subprocess
+
+    exe = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                       "paper_1110_3711_amd", "sph_run")
+    if not os.access(exe, os.X_OK):
+        pytest.skip("sph_run is not built")
+    out = tmp_path / "out.bin"
+    assert subprocess.run([exe], capture_output=True, timeout=60).returncode == 2
+    bad = tmp_path / "bad.bin"
+    bad.write_bytes(struct.pack("<3i", 5, 9, 1))
+    r = subprocess.run([exe, str(bad), str(out)], capture_output=True, text=True, timeout=60)
+    assert r.returncode == 1 and "bad header" in r.stderr
+    short = tmp_path / "short.bin"
+    short.write_bytes(struct.pack("<3i", 5, 2, 1) + b"\0" * 16)
+    r = subprocess.run([exe, str(short), str(out)], capture_output=True, text=True, timeout=60)
+    assert r.returncode == 1 and "too short" in r.stderr
+    assert not out.exists()
