@@ -55,7 +55,8 @@ def test_cubic_forces_match_oracle(ora, nsub):
     assert int(sim.npairs.sum().item()) == npairs
 
 
-def test_cubic_interact_backward_matches_oracle(ora):
+@pytest.mark.parametrize("nsub", [1, 2])
+def test_cubic_interact_backward_matches_oracle(ora, nsub):
     import torch
 
     from paper_1110_3711_amd import sph
@@ -65,8 +66,8 @@ def test_cubic_interact_backward_matches_oracle(ora):
     rng = np.random.default_rng(5)
     lay.rho = lay.rho + rng.normal(0, 2.0, lay.n)
     lay.rho[: lay.nb] = np.abs(lay.rho[: lay.nb] - lay.phys.rho0) + lay.phys.rho0
-    print(f"cubic interact_backward n={lay.n}", flush=True)
-    sim = sph.Simulation(lay, nsub=1)
+    print(f"cubic interact_backward nsub={nsub} n={lay.n}", flush=True)
+    sim = sph.Simulation(lay, nsub=nsub)
     sim.build_cells()
     w = rng.normal(size=(lay.n, 4))
     w[: lay.nb, :3] = 0.0

@@ -24,15 +24,16 @@ def _layout(kernel=0, dp=0.01, seed=SEED_BASE + 1, vel=0.2, vel_seed=79, rho_sig
     return L
 
 
-@pytest.mark.parametrize("kernel", [0, 1], ids=["wendland", "cubic"])
-def test_tensile_forces_match_oracle(ora, kernel):
+@pytest.mark.parametrize("kernel,nsub", [(0, 1), (1, 1), (0, 2)],
+                         ids=["wendland", "cubic", "wendland_nsub2"])
+def test_tensile_forces_match_oracle(ora, kernel, nsub):
     import torch
 
     from paper_1110_3711_amd import sph
 
     lay = _layout(kernel)
-    print(f"tensile interact kernel={kernel} n={lay.n}", flush=True)
-    sim = sph.Simulation(lay, nsub=1)
+    print(f"tensile interact kernel={kernel} nsub={nsub} n={lay.n}", flush=True)
+    sim = sph.Simulation(lay, nsub=nsub)
     sim.build_cells()
     sim.npairs.zero_()
     sim.interact()
@@ -56,16 +57,17 @@ def test_tensile_forces_match_oracle(ora, kernel):
     assert int(sim.npairs.sum().item()) == npairs
 
 
-@pytest.mark.parametrize("kernel", [0, 1], ids=["wendland", "cubic"])
-def test_tensile_interact_backward_matches_oracle(ora, kernel):
+@pytest.mark.parametrize("kernel,nsub", [(0, 1), (1, 1), (1, 2)],
+                         ids=["wendland", "cubic", "cubic_nsub2"])
+def test_tensile_interact_backward_matches_oracle(ora, kernel, nsub):
     import torch
 
     from paper_1110_3711_amd import sph
 
     lay = _layout(kernel, dp=0.02, seed=3, vel=0.3, vel_seed=4, rho_sigma=2.0,
                   fluid=(0.12, 0.12, 0.12), tank=(0.2, 0.14, 0.14))
-    print(f"tensile interact_backward kernel={kernel} n={lay.n}", flush=True)
-    sim = sph.Simulation(lay, nsub=1)
+    print(f"tensile interact_backward kernel={kernel} nsub={nsub} n={lay.n}", flush=True)
+    sim = sph.Simulation(lay, nsub=nsub)
     sim.build_cells()
     rng = np.random.default_rng(21)
     w = rng.normal(size=(lay.n, 4))
