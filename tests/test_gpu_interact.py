@@ -6,6 +6,8 @@
 * Determinism: two launches are bitwise identical.
 """
 
+import dataclasses
+
 import numpy as np
 import pytest
 
@@ -109,7 +111,8 @@ def test_forces_compressed_several_tiles(ora):
     _compare_forces(ora, lay, sim)
 
 
-@pytest.mark.parametrize("which", ["dam_break_8k", "dam_break_8k_nsub2", "compressed"])
+@pytest.mark.parametrize("which", ["dam_break_8k", "dam_break_8k_nsub2", "compressed",
+                                   "cubic_tensile"])
 def test_range_table_path_bitwise(ora, which):
     """With the precomputed interaction ranges the pair kernels read each
     cell's runs from its row: forces, visc, pair counts and the pair VJP are
@@ -123,6 +126,8 @@ def test_range_table_path_bitwise(ora, which):
                                  vel_sigma=0.2, vel_seed=5), 0.5)
     else:
         lay = dam_break(0.01, 11103711 + 1, vel_sigma=0.2, vel_seed=77)
+    if which == "cubic_tensile":
+        lay.phys = dataclasses.replace(lay.phys, kernel=1, alpha=0.25, tensile_dp=lay.phys.dp)
     nsub = 2 if which.endswith("nsub2") else 1
     print(f"interact range table {which} n={lay.n}", flush=True)
     out = []
