@@ -2,8 +2,9 @@
 
 The binding only marshals arguments: every stage of the step runs in the HIP
 kernels of the library.  PyTorch provides device memory (tensors) and the HIP
-stream (``torch.cuda.current_stream()``).  If the library has not been built
-the import of this module fails loudly; there is no CPU fallback.
+stream (``torch.cuda.current_stream()``).  If the library has not been built,
+``load()`` (called by every entry point and by ``Simulation``) raises; there is
+no CPU fallback.
 """
 
 from __future__ import annotations
