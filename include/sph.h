@@ -53,7 +53,8 @@
 extern "C" {
 #endif
 
-#define SPH_ABI_VERSION 4 /* 2: two-entry npairs; 3: sph_params.tensile_dp; 4: sph_cells.ranges */
+#define SPH_ABI_VERSION 5 /* 2: two-entry npairs; 3: sph_params.tensile_dp; 4: sph_cells.ranges;
+                            5: SPH_DEV_BOUNDARY_OUT */
 #define SPH_API __attribute__((visibility("default")))
 #define SPH_EXCLUDED INT32_MAX /* cell index of a particle outside the domain */
 
@@ -67,7 +68,12 @@ typedef enum {
 /* bits OR-ed into *dev_status by the kernels */
 enum {
     SPH_DEV_OUT_OF_GRID = 1, /* a particle left the domain and is now excluded */
-    SPH_DEV_NONFINITE = 2    /* non-finite acceleration/time step; state kept  */
+    SPH_DEV_NONFINITE = 2,   /* non-finite acceleration/time step; state kept  */
+    SPH_DEV_BOUNDARY_OUT = 4 /* INVALID STATE: a boundary slot [0, nb) holds a particle
+                                outside the domain (cell SPH_EXCLUDED).  Boundary particles
+                                never move, so this can only come from the input; the
+                                sorted layout (boundary slots first) cannot hold it and
+                                every later output is meaningless.  Refuse such input. */
 };
 
 /* Cell grid of the neighbour list (Section 2: domain divided into cells so the
@@ -176,7 +182,9 @@ SPH_API int32_t sph_abi_version(void);
  * v [3n], rho [n]; ids [0, nb) are boundary particles).  Position encoding:
  * d = x - origin, k = floor(d / cell), offset = fp32(fma(-(k + 1/2), cell, d));
  * a particle outside [origin, hi) gets cell SPH_EXCLUDED and sets
- * SPH_DEV_OUT_OF_GRID.  velrho_prev = velrho, pos.w = P/rho^2, id = index. */
+ * SPH_DEV_OUT_OF_GRID, and also SPH_DEV_BOUNDARY_OUT if it is a boundary
+ * particle (an invalid input: the caller must not use the state).
+ * velrho_prev = velrho, pos.w = P/rho^2, id = index. */
 SPH_API sph_status sph_encode(const sph_grid *g, const sph_params *p, const double *x,
                       const double *v, const double *rho, sph_state *st, int32_t *dev_status,
                       hipStream_t stream);
@@ -187,7 +195,9 @@ SPH_API sph_status sph_decode(const sph_grid *g, const sph_params *p, const sph_
                       double *v, double *rho, hipStream_t stream);
 
 /* NL (Section 4.1): key = (slot < nb ? 0 : ncell) + cell, or 2 ncell when
- * excluded; stable LSD radix sort of (key, slot), ties keeping the src order;
+ * excluded (a boundary slot with cell SPH_EXCLUDED sets SPH_DEV_BOUNDARY_OUT:
+ * invalid input, outputs meaningless but every access stays in bounds);
+ * stable LSD radix sort of (key, slot), ties keeping the src order;
  * cell ranges and the list of non-empty keys; gather of every state array
  * into dst in sorted order.  perm[i] = src slot of dst slot i.  src and dst
  * must not overlap.  dst->n and dst->nb are set from src. */

@@ -56,7 +56,7 @@ def lib():
         L = C.CDLL(_LIB)
         dp, ip, i64p, u8p = (C.POINTER(C.c_double), C.POINTER(C.c_int32),
                              C.POINTER(C.c_int64), C.POINTER(C.c_uint8))
-        fp, u32p, pp = C.POINTER(C.c_float), C.POINTER(C.c_uint32), C.POINTER(Params)
+        fp, pp = C.POINTER(C.c_float), C.POINTER(Params)
         L.ora_w.argtypes = [pp, C.c_double]
         L.ora_w.restype = C.c_double
         L.ora_f.argtypes = [pp, C.c_double]
@@ -82,8 +82,6 @@ def lib():
         L.ora_encode.restype = None
         L.ora_decode.argtypes = [C.c_int, ip, fp, dp, C.c_double, ip, dp]
         L.ora_decode.restype = None
-        L.ora_count_f32.argtypes = [C.c_int, C.c_int, ip, fp, ip, C.c_float, C.c_float, ip, u32p]
-        L.ora_count_f32.restype = C.c_longlong
         L.ora_fprime.argtypes = [pp, C.c_double]
         L.ora_fprime.restype = C.c_double
         L.ora_interact_vjp.argtypes = [C.c_int, C.c_int, dp, dp, dp, u8p, pp, dp, dp, dp, dp, dp]
@@ -268,18 +266,6 @@ def decode(cidx, off, origin, cell, nc):
     lib().ora_decode(n, _p(cidx, C.c_int32), _p(off, C.c_float), _p(org, C.c_double),
                      float(cell), _p(ncv, C.c_int32), _p(x, C.c_double))
     return x
-
-
-def count_f32(cidx, off, nb, nc, cellf, rc2f):
-    cidx = np.ascontiguousarray(cidx, dtype=np.int32)
-    off = np.ascontiguousarray(off, dtype=np.float32).reshape(-1, 3)
-    n = cidx.size
-    ncv = np.ascontiguousarray(nc, dtype=np.int32)
-    cnt = np.zeros(n, dtype=np.int32)
-    hs = np.zeros(n, dtype=np.uint32)
-    tot = lib().ora_count_f32(n, nb, _p(cidx, C.c_int32), _p(off, C.c_float), _p(ncv, C.c_int32),
-                              float(cellf), float(rc2f), _p(cnt, C.c_int32), _p(hs, C.c_uint32))
-    return cnt, hs, tot
 
 
 def interact_vjp(x, v, rho, nb, P, abar, excl=None):

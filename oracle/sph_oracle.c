@@ -525,56 +525,6 @@ ORA_EXPORT void ora_decode(int n, const int32_t *cellidx, const float *off, cons
 }
 
 /* ------------------------------------------------------------------------ */
-/* Neighbour decision in FP32 from the encoded positions, by brute force over
- * all pairs: the same rule as N(a) but with the distance formed as
- *   s = fp32(dk) * cellf,  b' = o_b + s,  r = o_a - b'  (per axis, FP32),
- *   r2 = fmaf(rz, rz, fmaf(ry, ry, rx * rx)),  neighbour iff r2 < rc2f,
- * dk = k_b - k_a per axis.  This is the precision in which the GPU path takes
- * the same integer decision, so per-target counts and id hashes
- * (sum of uint32(id * 2654435761)) must agree exactly.                      */
-ORA_EXPORT long long ora_count_f32(int n, int nb, const int32_t *cellidx, const float *off,
-                                   const int32_t *nc, float cellf, float rc2f, int32_t *count,
-                                   uint32_t *idhash)
-{
-    int32_t *kk = (int32_t *)malloc(sizeof(int32_t) * 3 * (size_t)(n > 0 ? n : 1));
-    for (int i = 0; i < n; ++i) {
-        const long long c = cellidx[i];
-        if (c == ORA_EXCLUDED) { kk[3 * i] = kk[3 * i + 1] = kk[3 * i + 2] = 0; continue; }
-        kk[3 * i] = (int32_t)(c % nc[0]);
-        kk[3 * i + 1] = (int32_t)((c / nc[0]) % nc[1]);
-        kk[3 * i + 2] = (int32_t)(c / ((long long)nc[0] * nc[1]));
-    }
-    long long total = 0;
-#pragma omp parallel for schedule(dynamic, 16) reduction(+ : total)
-    for (int a = 0; a < n; ++a) {
-        int32_t cnt = 0;
-        uint32_t hs = 0;
-        if (cellidx[a] != ORA_EXCLUDED) {
-            const float ax = off[3 * a], ay = off[3 * a + 1], az = off[3 * a + 2];
-            for (int b = 0; b < n; ++b) {
-                if (b == a || cellidx[b] == ORA_EXCLUDED) continue;
-                if (a < nb && b < nb) continue;
-                const float sx = (float)(kk[3 * b] - kk[3 * a]) * cellf;
-                const float sy = (float)(kk[3 * b + 1] - kk[3 * a + 1]) * cellf;
-                const float sz = (float)(kk[3 * b + 2] - kk[3 * a + 2]) * cellf;
-                const float bx = off[3 * b] + sx, by = off[3 * b + 1] + sy, bz = off[3 * b + 2] + sz;
-                const float rx = ax - bx, ry = ay - by, rz = az - bz;
-                const float r2 = fmaf(rz, rz, fmaf(ry, ry, rx * rx));
-                if (r2 < rc2f) {
-                    ++cnt;
-                    hs += (uint32_t)b * 2654435761u;
-                }
-            }
-        }
-        count[a] = cnt;
-        idhash[a] = hs;
-        total += cnt;
-    }
-    free(kk);
-    return total;
-}
-
-/* ------------------------------------------------------------------------ */
 /* Derivative of the kernel gradient factor: dF/dr.  Pinned by: finite
  * differences of ora_f.                                                       */
 ORA_EXPORT double ora_fprime(const ora_params *p, double r)

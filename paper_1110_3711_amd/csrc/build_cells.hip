@@ -36,7 +36,7 @@ __device__ inline uint32_t key_of(const KeySrc &S, int64_t i)
 
 __global__ __launch_bounds__(kSortThreads) void k_radix_hist(int32_t n, int shift, KeySrc keys,
                                                              uint32_t *__restrict__ hist,
-                                                             int nblk)
+                                                             int nblk, int32_t *dev_status)
 {
     __shared__ uint32_t h[kRadix];
     for (int d = threadIdx.x; d < kRadix; d += kSortThreads) h[d] = 0;
@@ -44,7 +44,12 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_hist(int32_t n, int shif
     const int64_t base = (int64_t)blockIdx.x * kSortTile;
     for (int j = 0; j < kSortItems; ++j) {
         const int64_t e = base + (int64_t)j * kSortThreads + threadIdx.x;
-        if (e < n) atomicAdd(&h[(key_of(keys, e) >> shift) & (kRadix - 1)], 1u);
+        if (e < n) {
+            atomicAdd(&h[(key_of(keys, e) >> shift) & (kRadix - 1)], 1u);
+            // first pass: a boundary slot must hold a particle inside the grid
+            if (!keys.keys && e < keys.nb && keys.cell[e] == SPH_EXCLUDED)
+                atomicOr(dev_status, SPH_DEV_BOUNDARY_OUT);
+        }
     }
     __syncthreads();
     for (int d = threadIdx.x; d < kRadix; d += kSortThreads)
@@ -358,7 +363,6 @@ hipError_t launch_build_cells(const sph_grid *g, const sph_state *src, sph_state
                               sph_cells *cells, int32_t *perm, const Workspace &w,
                               int32_t *dev_status, hipStream_t s)
 {
-    (void)dev_status;
     const int32_t n = src->n;
     const int32_t ncell = (int32_t)ncell_of(g);
     const int64_t nkeys = 2 * (int64_t)ncell + 1;  // keys 0 .. 2 ncell
@@ -374,7 +378,7 @@ hipError_t launch_build_cells(const sph_grid *g, const sph_state *src, sph_state
     const int nblk = nblk_sort(n);
     for (int shift = 0; shift < bits && n > 0; shift += kRadixBits) {
         const KeySrc ks{kin, src->cell, src->nb, ncell};
-        k_radix_hist<<<nblk, kSortThreads, 0, s>>>(n, shift, ks, w.hist, nblk);
+        k_radix_hist<<<nblk, kSortThreads, 0, s>>>(n, shift, ks, w.hist, nblk, dev_status);
         hipError_t e = exclusive_scan<uint32_t>(w.hist, (int64_t)kRadix * nblk, w.partials, s);
         if (e != hipSuccess) return e;
         k_radix_scatter<<<nblk, kSortThreads, 0, s>>>(n, shift, ks, vin, kout, vout, w.hist, nblk);

@@ -21,7 +21,8 @@ static GridD grid_d(const sph_grid *g)
     return d;
 }
 
-__global__ void k_encode(GridD G, double rho0, double B, int32_t n, const double *__restrict__ x,
+__global__ void k_encode(GridD G, double rho0, double B, int32_t n, int32_t nb,
+                         const double *__restrict__ x,
                          const double *__restrict__ v, const double *__restrict__ rho,
                          int32_t *__restrict__ cell, float4 *__restrict__ pos,
                          float4 *__restrict__ velrho, float4 *__restrict__ velrho_prev,
@@ -51,7 +52,8 @@ __global__ void k_encode(GridD G, double rho0, double B, int32_t n, const double
     if (!ok) {
         cell[i] = SPH_EXCLUDED;
         pos[i] = make_float4(0.f, 0.f, 0.f, pw);
-        atomicOr(dev_status, SPH_DEV_OUT_OF_GRID);
+        atomicOr(dev_status, i < nb ? SPH_DEV_OUT_OF_GRID | SPH_DEV_BOUNDARY_OUT
+                                    : SPH_DEV_OUT_OF_GRID);
         return;
     }
     cell[i] = (int32_t)(k[0] + (int64_t)G.nc[0] * (k[1] + (int64_t)G.nc[1] * k[2]));
@@ -90,7 +92,7 @@ hipError_t launch_encode(const sph_grid *g, const sph_params *p, const double *x
     const double B = p->c0 * p->c0 * p->rho0 / p->gamma;
     const int threads = 256;
     const int blocks = (st->n + threads - 1) / threads;
-    k_encode<<<blocks, threads, 0, s>>>(grid_d(g), p->rho0, B, st->n, x, v, rho, st->cell,
+    k_encode<<<blocks, threads, 0, s>>>(grid_d(g), p->rho0, B, st->n, st->nb, x, v, rho, st->cell,
                                         (float4 *)st->pos, (float4 *)st->velrho,
                                         (float4 *)st->velrho_prev, st->id, dev_status);
     return hipGetLastError();

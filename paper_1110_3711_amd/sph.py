@@ -18,11 +18,11 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libsph.so")
 
 SPH_OK, SPH_ERR_ARG, SPH_ERR_WORKSPACE, SPH_ERR_HIP = 0, 1, 2, 3
-SPH_DEV_OUT_OF_GRID, SPH_DEV_NONFINITE = 1, 2
+SPH_DEV_OUT_OF_GRID, SPH_DEV_NONFINITE, SPH_DEV_BOUNDARY_OUT = 1, 2, 4
 SPH_FIXED_DT, SPH_ADJOINT = 1, 2
 SPH_PI_FLUID, SPH_PI_BOUNDARY, SPH_PI_ALL = 1, 2, 3
 SPH_EXCLUDED = 2**31 - 1
-ABI_VERSION = 4
+ABI_VERSION = 5
 
 EXPORTS = ["sph_workspace_bytes", "sph_ranges_bytes", "sph_abi_version", "sph_encode", "sph_decode",
            "sph_build_cells", "sph_interact", "sph_step", "sph_interact_backward",
@@ -353,6 +353,9 @@ class Simulation:
         rd = torch.as_tensor(np.ascontiguousarray(rho, dtype=np.float64)).to(self.device)
         sph_encode(self.grid, self.params, xd, vd, rd, self.a.c(), self.status)
         torch.cuda.current_stream().synchronize()
+        if self.dev_status() & SPH_DEV_BOUNDARY_OUT:
+            raise SphError("a boundary particle lies outside the domain: boundary particles "
+                           "must lie inside the grid (they never move)")
 
     def upload_prev(self, v_prev, rho_prev):
         """Set level n-1 (velrho_prev) from FP64 arrays in id order (current

@@ -11,7 +11,7 @@
 import numpy as np
 import pytest
 
-from _helpers import compress, grid_tuple, oracle_view, rel_l2
+from _helpers import compress, grid_tuple, oracle_view, parity, rel_l2
 from sph_inputs import dam_break, named_case
 
 pytestmark = pytest.mark.gpu
@@ -62,6 +62,8 @@ def test_interact_backward_matches_oracle(ora, which):
     w32 = w.astype(np.float32).astype(np.float64)
     oxb, ovb, orb, oab = ora.interact_vjp(xq, vq, rq, lay.nb, ora.params(lay.phys), w32, excl)
     f = slice(lay.nb, None)
+    parity(f"VJP {which}", xbar=(gx[f, :3], oxb[f]), vbar=(gv[f, :3], ovb[f]),
+           rhobar=(gv[:, 3], orb))
     ex = rel_l2(gx[f, :3], oxb[f])
     ev = rel_l2(gv[f, :3], ovb[f])
     er = rel_l2(gv[:, 3], orb)

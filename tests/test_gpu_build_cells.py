@@ -148,3 +148,35 @@ def test_range_table_8k(ora, nsub):
     assert np.array_equal(got[cells], want)
     empty = np.setdiff1d(np.arange(sim.ncell), cells)
     assert np.all(got[empty] == -7)
+
+
+def test_boundary_particle_outside_domain_is_refused(ora):
+    """A wall particle outside the domain cannot be held by the sorted layout
+    (boundary slots first, excluded particles last): sph_encode and
+    sph_build_cells flag SPH_DEV_BOUNDARY_OUT, and the binding refuses the
+    layout."""
+    import torch
+
+    from paper_1110_3711_amd import sph
+
+    lay = dam_break(0.02, 3)
+    lay.x[0, 2] = lay.lo[2] - 0.01  # boundary id 0 below the domain
+    print("build_cells: boundary particle outside the domain", flush=True)
+    with pytest.raises(sph.SphError, match="boundary particle"):
+        sph.Simulation(lay)
+    # the same condition in a state filled by the caller: a boundary slot
+    # (ids [0, nb) are slots [0, nb) straight after encoding) with an
+    # excluded cell
+    sim = sph.Simulation(dam_break(0.02, 3))
+    assert sim.dev_status() == 0
+    sim.a.cell[5] = sph.SPH_EXCLUDED
+    sim.build_cells()
+    torch.cuda.synchronize()
+    assert sim.dev_status() & sph.SPH_DEV_BOUNDARY_OUT
+    # fluid particles outside the domain are merely excluded
+    lay3 = dam_break(0.02, 3)
+    lay3.x[lay3.nb, 2] = lay3.lo[2] - 0.01
+    sim3 = sph.Simulation(lay3)
+    sim3.build_cells()
+    torch.cuda.synchronize()
+    assert sim3.dev_status() == sph.SPH_DEV_OUT_OF_GRID

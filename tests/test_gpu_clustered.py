@@ -19,7 +19,7 @@ import time
 import numpy as np
 import pytest
 
-from _helpers import grid_tuple, oracle_view, rel_l2
+from _helpers import elem_err, grid_tuple, oracle_view, rel_l2
 from sph_inputs import CLUSTER_SEED, SEED_BASE, named_case, refine
 
 pytestmark = pytest.mark.gpu
@@ -74,9 +74,10 @@ def _gpu_forces(lay, x_dev, stats=False):
 
 
 def _errors(ace, visc, ref, rvisc, tgt, nb):
+    """(rel L2, per-element) of the fluid accelerations, drho/dt and visc."""
     fl = tgt >= nb
-    return (rel_l2(ace[tgt[fl], :3], ref[fl, :3]), rel_l2(ace[tgt, 3], ref[:, 3]),
-            rel_l2(visc[tgt[fl]], rvisc[fl]))
+    pairs = ((ace[tgt[fl], :3], ref[fl, :3]), (ace[tgt, 3], ref[:, 3]), (visc[tgt[fl]], rvisc[fl]))
+    return tuple(rel_l2(a, b) for a, b in pairs), tuple(elem_err(a, b) for a, b in pairs)
 
 
 def _policy_errors(ora, lay, tgt, label):
@@ -97,10 +98,21 @@ def _policy_errors(ora, lay, tgt, label):
     x32 = lay.x.astype(np.float32).astype(np.float64)
     ace3, visc3, _, _, _ = _gpu_forces(lay, x32)
     res["iii_true"] = _errors(ace3, visc3, ref, rvisc, tgt, lay.nb)
-    for k, (ea, ed, ev) in res.items():
-        print(f"  {label} policy {k:13s}: rel L2 acc {ea:.2e} drho {ed:.2e} visc {ev:.2e}",
-              flush=True)
+    for k, ((ea, ed, ev), (ma, md, mv)) in res.items():
+        print(f"  {label} policy {k:13s}: rel L2 acc {ea:.2e} drho {ed:.2e} visc {ev:.2e}; "
+              f"per-element max acc {ma:.2e} drho {md:.2e} visc {mv:.2e}", flush=True)
     return res, npairs, cnt
+
+
+def _assert_policies(res):
+    """(i) within the parity bar on both references; naive FP32 absolute
+    positions (iii) clearly worse than (i) against the FP64 truth."""
+    for k in ("i_true", "i_same_state"):
+        l2, el = res[k]
+        assert max(l2) <= 1e-4 and max(el) <= 1e-3, (k, l2, el)
+    (a1, _, v1), _ = res["i_true"]
+    (a3, _, v3), _ = res["iii_true"]
+    assert a3 >= 5 * a1 and v3 >= 20 * v1, (a1, a3, v1, v3)
 
 
 def test_clustered_position_policies(ora, clustered):
@@ -115,7 +127,7 @@ def test_clustered_position_policies(ora, clustered):
     hist, edges = np.histogram(fl, bins=[0, 20, 60, 120, 200, 300, 400, 600, 800, 1200, 10 ** 6])
     print("  histogram:", ", ".join(f"[{int(a)},{int(b)}): {c}" for a, b, c in
                                      zip(edges[:-1], edges[1:], hist)), flush=True)
-    assert max(res["i_true"]) <= 1e-4 and max(res["i_same_state"]) <= 1e-4
+    _assert_policies(res)
 
     # step 1: one FP64 oracle step from the snapshot, then the same comparisons
     S = ora.State(lay)
@@ -125,7 +137,7 @@ def test_clustered_position_policies(ora, clustered):
     lay1 = lay.copy()
     lay1.x, lay1.v, lay1.rho = S.x.copy(), S.v.copy(), S.rho.copy()
     res1, _, _ = _policy_errors(ora, lay1, tgt, "step 1")
-    assert max(res1["i_true"]) <= 1e-4 and max(res1["i_same_state"]) <= 1e-4
+    _assert_policies(res1)
 
 
 def test_clustered_step_timing(clustered):

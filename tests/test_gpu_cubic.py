@@ -9,7 +9,7 @@ gradients vs central finite differences of the oracle <= 1e-3.
 import numpy as np
 import pytest
 
-from _helpers import grid_tuple, oracle_view, rel_l2
+from _helpers import grid_tuple, oracle_view, parity, rel_l2
 from sph_inputs import SEED_BASE, dam_break
 
 pytestmark = pytest.mark.gpu
@@ -43,11 +43,8 @@ def test_cubic_forces_match_oracle(ora, nsub):
     ref, rvisc, _, npairs = ora.interact(xq, vq, rq, lay.nb, P, excl=excl)
     ace, visc = sim.by_id(sim.ace), sim.by_id(sim.visc)
     f = np.arange(lay.nb, lay.n)
-    e_a = rel_l2(ace[f, :3], ref[f, :3])
-    e_d = rel_l2(ace[:, 3], ref[:, 3])
-    e_v = rel_l2(visc, rvisc)
-    print(f"  rel L2: acc {e_a:.2e} drho {e_d:.2e} visc {e_v:.2e}", flush=True)
-    assert e_a <= 1e-4 and e_d <= 1e-4 and e_v <= 1e-4
+    parity(f"cubic nsub={nsub}", acc=(ace[f, :3], ref[f, :3]), drho=(ace[:, 3], ref[:, 3]),
+           visc=(visc, rvisc))
     # the Wendland forces differ: the switch reached the kernels
     Pw = ora.params(lay.phys, kernel=0)
     refw, *_ = ora.interact(xq, vq, rq, lay.nb, Pw, excl=excl)
@@ -85,6 +82,8 @@ def test_cubic_interact_backward_matches_oracle(ora, nsub):
     oxb, ovb, orb, oab = ora.interact_vjp(xq, vq, rq, lay.nb, ora.params(lay.phys), w32, excl)
     gx, gv = sim.by_id(xb), sim.by_id(vb)
     f = slice(lay.nb, None)
+    parity(f"cubic VJP nsub={nsub}", xbar=(gx[f, :3], oxb[f]), vbar=(gv[f, :3], ovb[f]),
+           rhobar=(gv[:, 3], orb))
     ex, ev = rel_l2(gx[f, :3], oxb[f]), rel_l2(gv[f, :3], ovb[f])
     er, ea = rel_l2(gv[:, 3], orb), abs(ab.item() - oab) / abs(oab)
     print(f"  rel L2: xbar {ex:.2e} vbar {ev:.2e} rhobar {er:.2e} alphabar {ea:.2e}", flush=True)

@@ -1,8 +1,10 @@
 """sph_interact on the GPU against the FP64 oracle on the same encoded state.
 
-* Neighbour sets: per-target count and id hash equal the oracle's brute-force
-  FP32-decision count exactly (same precision, same distance expression).
-* Forces: relative L2 <= 1e-4 for fluid accelerations, drho/dt and visc.
+* Neighbour sets: per-target count and id hash lie between the oracle's FP64
+  cell-list sets at the cutoff moved by -1e-5 and +1e-5 (relative, in r^2):
+  exact for every target without a pair in that tie band.
+* Forces: relative L2 <= 1e-4 and per-target error <= 1e-3 of the rms for
+  fluid accelerations, drho/dt and visc.
 * Determinism: two launches are bitwise identical.
 """
 
@@ -11,7 +13,7 @@ import dataclasses
 import numpy as np
 import pytest
 
-from _helpers import compress, grid_tuple, oracle_view, rel_l2
+from _helpers import band_sets, check_sets_in_band, compress, grid_tuple, oracle_view, parity
 from sph_inputs import blob, dam_break, named_case
 
 pytestmark = pytest.mark.gpu
@@ -41,30 +43,29 @@ def _compare_forces(ora, lay, sim, tol=TOL):
     visc = sim.by_id(sim.visc)
     f = np.arange(lay.nb, lay.n)
     f = f[excl[f] == 0]
-    e_a = rel_l2(ace[f, :3], ref[f, :3])
-    e_d = rel_l2(ace[:, 3], ref[:, 3])
-    e_v = rel_l2(visc, rvisc)
-    print(f"  rel L2: acc {e_a:.2e} drho {e_d:.2e} visc {e_v:.2e}", flush=True)
-    assert e_a <= tol and e_d <= tol and e_v <= tol
+    parity(f"{lay.name} n={lay.n}", tol=tol, acc=(ace[f, :3], ref[f, :3]),
+           drho=(ace[:, 3], ref[:, 3]), visc=(visc, rvisc))
     assert np.all(ace[excl == 1] == 0)
     assert np.all(ace[: lay.nb, :3] == 0) and np.all(visc[: lay.nb] == 0)
     return npairs
 
 
 @pytest.mark.parametrize("nsub", [1, 2])
-def test_neighbour_sets_bit_exact(ora, nsub):
+def test_neighbour_sets_within_tie_band(ora, nsub):
     lay = named_case("dam_break_8k")
     print(f"interact stats dam_break_8k nsub={nsub}", flush=True)
     sim, st = _run(lay, nsub, stats=True)
     gt = grid_tuple(sim)
-    _, _, _, _, cidx, off = oracle_view(ora, lay.x, lay.v, lay.rho, lay.phys.rho0, gt, lay.lo,
-                                        lay.hi)
-    rc2 = np.float32(4.0 * lay.phys.h * lay.phys.h)
-    cnt, hs, tot = ora.count_f32(cidx, off, lay.nb, gt[2], np.float32(gt[1]), rc2)
+    xq, _, _, excl, _, _ = oracle_view(ora, lay.x, lay.v, lay.rho, lay.phys.rho0, gt, lay.lo,
+                                       lay.hi)
+    inner, outer = band_sets(ora, xq, lay.nb, lay.phys.h, excl=excl)
     s = sim.by_id(st.view(-1, 2))
-    assert np.array_equal(s[:, 0], cnt)
-    assert np.array_equal(s[:, 1].view(np.uint32), hs)
-    assert int(sim.npairs.sum().item()) == tot
+    tied, nband = check_sets_in_band(s[:, 0], s[:, 1].view(np.uint32), inner, outer)
+    total = int(sim.npairs.sum().item())
+    print(f"  {total:,} directed pairs; {nband} FP64 pairs in the tie band on {tied} targets",
+          flush=True)
+    assert int(s[:, 0].sum()) == total
+    assert inner[0][-1] <= total <= outer[0][-1]
 
 
 @pytest.mark.parametrize("nsub", [1, 2])
@@ -85,7 +86,7 @@ def test_forces_8k_rest(ora):
     ref, rvisc, _, _ = ora.interact(xq, vq, rq, lay.nb, ora.params(lay.phys), excl=excl)
     ace = sim.by_id(sim.ace)
     f = slice(lay.nb, None)
-    assert rel_l2(ace[f, :3], ref[f, :3]) <= TOL
+    parity("dam_break_8k rest", acc=(ace[f, :3], ref[f, :3]))
     assert np.all(ace[:, 3] == 0) and np.all(ref[:, 3] == 0)  # at rest: no density change
 
 
@@ -153,13 +154,15 @@ def test_range_table_path_bitwise(ora, which):
 
 
 def test_momentum_conservation_gpu(ora):
-    # pair forces are antisymmetric; the FP32 sum of internal forces over a
-    # free blob vanishes to FP32 rounding
+    # pair forces are antisymmetric; the sum of the FP32 internal forces over a
+    # free blob (no gravity, no boundary) vanishes to FP32 rounding
     lay = blob(16, 0.01, 8, vel_sigma=0.3, jitter=0.3)
     print("interact momentum blob", flush=True)
     sim, _ = _run(lay, 1)
     a = sim.by_id(sim.ace)[:, :3].astype(np.float64)
-    assert np.abs(a.sum(0)).max() <= 1e-5 * np.abs(a).sum()
+    res = np.abs(a.sum(0)).max() / np.abs(a).sum()
+    print(f"  |sum m a| / sum |m a| = {res:.2e}", flush=True)
+    assert res <= 1e-6
 
 
 def test_determinism(ora):

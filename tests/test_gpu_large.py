@@ -9,7 +9,7 @@ import dataclasses
 import numpy as np
 import pytest
 
-from _helpers import grid_tuple, oracle_view, rel_l2
+from _helpers import grid_tuple, oracle_view, parity
 from sph_inputs import SEED_BASE, dam_break
 
 pytestmark = pytest.mark.gpu
@@ -38,12 +38,9 @@ def _subset_parity(ora, lay, nsub, nsample=65536, seed=0):
     ref, rvisc, _, _ = ora.interact(xq, vq, rq, lay.nb, ora.params(lay.phys), excl=excl,
                                     targets=tgt)
     fl = tgt >= lay.nb
-    e_a = rel_l2(ace[tgt[fl], :3], ref[fl, :3])
-    e_d = rel_l2(ace[tgt, 3], ref[:, 3])
-    e_v = rel_l2(visc[tgt[fl]], rvisc[fl])
-    print(f"  {lay.name} n={lay.n}: rel L2 acc {e_a:.2e} drho {e_d:.2e} visc {e_v:.2e}",
-          flush=True)
-    return e_a, e_d, e_v
+    res = parity(f"{lay.name} n={lay.n}", acc=(ace[tgt[fl], :3], ref[fl, :3]),
+                 drho=(ace[tgt, 3], ref[:, 3]), visc=(visc[tgt[fl]], rvisc[fl]))
+    return tuple(e for e, _ in res.values())
 
 
 def _grid(lay, nsub):

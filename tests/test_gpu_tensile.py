@@ -9,7 +9,7 @@ import dataclasses
 import numpy as np
 import pytest
 
-from _helpers import grid_tuple, oracle_view, rel_l2
+from _helpers import grid_tuple, oracle_view, parity, rel_l2
 from sph_inputs import SEED_BASE, dam_break
 
 pytestmark = pytest.mark.gpu
@@ -45,6 +45,8 @@ def test_tensile_forces_match_oracle(ora, kernel, nsub):
     ref, rvisc, _, npairs = ora.interact(xq, vq, rq, lay.nb, P, excl=excl)
     ace, visc = sim.by_id(sim.ace), sim.by_id(sim.visc)
     f = np.arange(lay.nb, lay.n)
+    parity(f"tensile kernel={kernel} nsub={nsub}", acc=(ace[f, :3], ref[f, :3]),
+           drho=(ace[:, 3], ref[:, 3]), visc=(visc, rvisc))
     e_a = rel_l2(ace[f, :3], ref[f, :3])
     e_d = rel_l2(ace[:, 3], ref[:, 3])
     e_v = rel_l2(visc, rvisc)
@@ -86,6 +88,8 @@ def test_tensile_interact_backward_matches_oracle(ora, kernel, nsub):
     oxb, ovb, orb, oab = ora.interact_vjp(xq, vq, rq, lay.nb, ora.params(lay.phys), w32, excl)
     gx, gv = sim.by_id(xb), sim.by_id(vb)
     fs = slice(lay.nb, None)
+    parity(f"tensile VJP kernel={kernel} nsub={nsub}", xbar=(gx[fs, :3], oxb[fs]),
+           vbar=(gv[fs, :3], ovb[fs]), rhobar=(gv[:, 3], orb))
     ex, ev = rel_l2(gx[fs, :3], oxb[fs]), rel_l2(gv[fs, :3], ovb[fs])
     er, ea = rel_l2(gv[:, 3], orb), abs(ab.item() - oab) / abs(oab)
     print(f"  rel L2: xbar {ex:.2e} vbar {ev:.2e} rhobar {er:.2e} alphabar {ea:.2e}", flush=True)

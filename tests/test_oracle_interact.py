@@ -92,6 +92,70 @@ def test_approaching_pair_viscosity_and_continuity(ora):
     assert visc[0] == pytest.approx(abs(mu), rel=1e-12)
 
 
+def _monaghan_pair_expect(ora, P, ph, r, vrel, rhoa, rhob):
+    """Closed form of one approaching pair along x (x_a - x_b = r > 0,
+    v_a - v_b = vrel < 0) with unequal densities: the Monaghan term of the
+    Table 1 viscosity uses the arithmetic means of the two sound speeds and of
+    the two densities.  Every ingredient is pinned on its own: the kernel
+    factor F, the Tait pressure and the sound speed sqrt(dP/drho)."""
+    m, F, h = ph.mass, ora.kernel_f(P, r), ph.h
+    mu = h * (vrel * r) / (r * r + ph.eta2)
+    cbar = 0.5 * (ora.sound(P, rhoa) + ora.sound(P, rhob))
+    rbar = 0.5 * (rhoa + rhob)
+    Pi = -ph.alpha * cbar * mu / rbar
+    pa = ora.pressure(P, rhoa) / rhoa**2
+    pb = ora.pressure(P, rhob) / rhob**2
+    return m, F, mu, Pi, pa, pb
+
+
+def test_approaching_pair_unequal_densities_means(ora):
+    # rho_a = 1006, rho_b = 995: c and rho differ between the two ends, so the
+    # averaging of the Monaghan term matters (max(c) or a geometric mean of
+    # the densities would change Pi by about 1.6e-2 and 1.5e-5 relative).
+    ph = physics(0.01)
+    r, U = 1.15 * ph.h, 0.6
+    rhoa, rhob = 1006.0, 995.0
+    L = _pair_layout([0.5 + r, 0.5, 0.5], [0.5, 0.5, 0.5], [-U, 0, 0], [0, 0, 0], rhoa, rhob)
+    P = ora.params(L.phys)
+    ace, visc, _, npairs = ora.interact(L.x, L.v, L.rho, 0, P)
+    assert npairs == 2
+    m, F, mu, Pi, pa, pb = _monaghan_pair_expect(ora, P, ph, r, -U, rhoa, rhob)
+    assert Pi > 0 and mu < 0
+    ax = -m * (pa + pb + Pi) * F * r
+    assert ace[0, 0] == pytest.approx(ax, rel=1e-13)
+    assert ace[1, 0] == pytest.approx(-ax, rel=1e-13)       # the pair term is antisymmetric
+    assert ace[0, 3] == pytest.approx(m * (-U * r) * F, rel=1e-13)
+    assert ace[1, 3] == pytest.approx(ace[0, 3], rel=1e-13)
+    assert visc[0] == pytest.approx(abs(mu), rel=1e-13) and visc[1] == visc[0]
+    # the viscous part on its own: subtract the same pair at rest
+    L0 = _pair_layout([0.5 + r, 0.5, 0.5], [0.5, 0.5, 0.5], [0, 0, 0], [0, 0, 0], rhoa, rhob)
+    a0, *_ = ora.interact(L0.x, L0.v, L0.rho, 0, P)
+    assert ace[0, 0] - a0[0, 0] == pytest.approx(-m * Pi * F * r, rel=1e-9)
+
+
+def test_fluid_boundary_pair_unequal_densities_means(ora):
+    # fluid a (rho_a = 997, P_a < 0) moves down onto boundary b (rho_b = 1012):
+    # the fluid's acceleration carries the same averaged Monaghan term; the
+    # boundary target gets only its continuity rate.
+    ph = physics(0.01)
+    r, U = 0.95 * ph.h, 0.45
+    rhoa, rhob = 997.0, 1012.0
+    # id 0 is the boundary particle (nb = 1), id 1 the fluid particle above it
+    L = _pair_layout([0.5, 0.5, 0.5], [0.5, 0.5, 0.5 + r], [0, 0, 0], [0, 0, -U], rhob, rhoa)
+    P = ora.params(L.phys)
+    ace, visc, _, npairs = ora.interact(L.x, L.v, L.rho, 1, P)
+    assert npairs == 2
+    # seen from the fluid particle: r_ab = +r along z, v_ab = -U along z
+    m, F, mu, Pi, pa, pb = _monaghan_pair_expect(ora, P, ph, r, -U, rhoa, rhob)
+    assert pa < 0 < pb and Pi > 0
+    assert ace[1, 2] == pytest.approx(-9.81 - m * (pa + pb + Pi) * F * r, rel=1e-13)
+    assert ace[1, 0] == 0.0 and ace[1, 1] == 0.0
+    assert ace[1, 3] == pytest.approx(m * (-U * r) * F, rel=1e-13)
+    assert visc[1] == pytest.approx(abs(mu), rel=1e-13)
+    assert np.array_equal(ace[0, :3], [0.0, 0.0, 0.0]) and visc[0] == 0.0
+    assert ace[0, 3] == pytest.approx(ace[1, 3], rel=1e-13)
+
+
 def test_separating_pair_has_no_viscous_force(ora):
     ph = physics(0.01)
     r = 0.9 * ph.h

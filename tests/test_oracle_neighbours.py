@@ -1,11 +1,12 @@
-"""Pins of the oracle's neighbour search and of its FP32 decision variant.
+"""Pins of the oracle's neighbour search and of the tie-band set comparison.
 
 * The O(N^2) brute force and the cell list find identical neighbour sets, and
   with id-ordered summation give bit-identical FP64 forces (Section 2 stage NL
   is only an accelerator of the pair search).
 * No boundary-boundary pairs (Section 2).
-* The FP32 decision variant (the precision the GPU decides in) agrees with the
-  FP64 sets except on pairs whose distance is within rounding of the cutoff.
+* The tie-band check used against the device's neighbour sets accepts every
+  set between the FP64 sets at the cutoff moved by -delta and +delta, and
+  nothing else.
 """
 
 import numpy as np
@@ -68,31 +69,68 @@ def test_excluded_particles_never_interact(ora):
     assert not np.isin(cols, np.arange(L.nb + 100, L.nb + 200)).any()
 
 
-def test_fp32_decision_matches_fp64_sets(ora):
+def _fake_device(rp, cols, n):
+    """(count, id hash) per target of a CSR set, as the device reports them."""
+    from _helpers import id_hash
+
+    cnt = np.diff(rp).astype(np.int32)
+    hs = np.zeros(n, dtype=np.uint64)
+    rows = np.repeat(np.arange(n), np.diff(rp))
+    np.add.at(hs, rows, id_hash(cols))
+    return cnt, (hs & np.uint64(0xFFFFFFFF)).astype(np.uint32)
+
+
+def test_tie_band_check_accepts_only_sets_between_the_bands(ora):
+    from _helpers import BAND, band_sets, check_sets_in_band
+
+    # target 0 at the origin; particle 1 well inside, 2 inside the tie band
+    # (r^2 = 4h^2 (1 - BAND/4)), 3 inside the band beyond the cutoff, 4 outside
+    h = 0.01
+    rc = 2 * h
+    x = np.array([[0.0, 0.0, 0.0], [0.5 * rc, 0.0, 0.0], [0.0, rc * np.sqrt(1 - BAND / 4), 0.0],
+                  [0.0, 0.0, rc * np.sqrt(1 + BAND / 4)], [-rc * np.sqrt(1 + 4 * BAND), 0.0, 0.0]])
+    inner, outer = band_sets(ora, x, 0, h)
+    n = x.shape[0]
+
+    def dev(sets0):
+        rp = np.zeros(n + 1, dtype=np.int64)
+        rp[1] = len(sets0)
+        cols = np.array(sorted(sets0), dtype=np.int32)
+        rest_rp, rest_cols = ora.neighbour_csr(x, 0, h)
+        # rows of the other targets: the FP64 definition
+        rows = [list(sets0)] + [list(rest_cols[rest_rp[a]:rest_rp[a + 1]]) for a in range(1, n)]
+        rp = np.concatenate([[0], np.cumsum([len(r) for r in rows])])
+        cols = np.array([c for r in rows for c in sorted(r)], dtype=np.int32)
+        return _fake_device(rp, cols, n)
+
+    for ok in ({1, 2}, {1}, {1, 2, 3}, {1, 3}):
+        cnt, hs = dev(ok)
+        check_sets_in_band(cnt, hs, inner, outer)
+    for wrong in ({2}, {1, 2, 4}, {1, 2, 3, 4}, set()):
+        cnt, hs = dev(wrong)
+        try:
+            check_sets_in_band(cnt, hs, inner, outer)
+        except AssertionError:
+            continue
+        raise AssertionError(f"set {wrong} accepted")
+
+
+def test_tie_band_brackets_fp64_sets_8k(ora):
+    # the FP64 definition itself lies between the bands, and the band holds
+    # few pairs on the encoded 8k-fluid dam break
+    from _helpers import band_sets, check_sets_in_band
+
     L = named_case("dam_break_8k")
     for nsub in (1, 2):
         org, cell, nc = cell_grid(L, nsub)
         cidx, off = ora.encode(L.x, org, cell, nc, L.lo, L.hi)
         x = ora.decode(cidx, off, org, cell, nc)
-        rc2 = np.float32(4.0 * L.phys.h * L.phys.h)
-        cnt, hs, tot = ora.count_f32(cidx, off, L.nb, nc, np.float32(cell), rc2)
-        rp, cols = ora.neighbour_csr(x, L.nb, L.phys.h, mode=1)
-        c64 = np.diff(rp)
-        bad = np.nonzero(c64 != cnt)[0]
-        # every disagreement is a pair within rounding of the cutoff
-        for a in bad:
-            d2 = ((x[a] - x) ** 2).sum(1)
-            near = np.abs(d2 / (4 * L.phys.h**2) - 1.0) < 1e-6
-            assert abs(int(c64[a]) - int(cnt[a])) <= near.sum()
-        assert len(bad) <= 4
-        # hashes of agreeing sets agree
-        ids = np.arange(L.n, dtype=np.uint64)
-        hh = (ids * np.uint64(2654435761)) & np.uint64(0xFFFFFFFF)
-        for a in range(0, L.n, 211):
-            if a in bad:
-                continue
-            s = int(hh[cols[rp[a]:rp[a + 1]]].sum()) & 0xFFFFFFFF
-            assert s == int(hs[a])
+        inner, outer = band_sets(ora, x, L.nb, L.phys.h)
+        rp, cols = ora.neighbour_csr(x, L.nb, L.phys.h)
+        cnt, hs = _fake_device(rp, cols, L.n)
+        tied, nband = check_sets_in_band(cnt, hs, inner, outer)
+        assert rp[-1] > 2_000_000 and nband <= 1e-4 * rp[-1]
+        print(f"  nsub={nsub}: {nband} band pairs on {tied} targets of {rp[-1]:,} pairs")
 
 
 def test_stencil_superset(ora):
