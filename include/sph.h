@@ -18,6 +18,8 @@
  *   sph_step(SPH_ADJOINT)  transpose of the Verlet update;
  *   sph_build_cells_backward  transpose of the reorder of sph_build_cells.
  *   sph_encode/sph_decode  FP64 <-> device state conversion.
+ *   sph_conservation       FP64 global sums of the conservation laws
+ *                          (momentum, energy, internal force) on the device.
  *
  * Conventions shared by every entry point
  *   - Every array argument is a DEVICE pointer owned by the caller; struct
@@ -53,8 +55,8 @@
 extern "C" {
 #endif
 
-#define SPH_ABI_VERSION 5 /* 2: two-entry npairs; 3: sph_params.tensile_dp; 4: sph_cells.ranges;
-                            5: SPH_DEV_BOUNDARY_OUT */
+#define SPH_ABI_VERSION 6 /* 2: two-entry npairs; 3: sph_params.tensile_dp; 4: sph_cells.ranges;
+                            5: SPH_DEV_BOUNDARY_OUT; 6: sph_conservation */
 #define SPH_API __attribute__((visibility("default")))
 #define SPH_EXCLUDED INT32_MAX /* cell index of a particle outside the domain */
 
@@ -278,6 +280,31 @@ SPH_API sph_status sph_interact_backward(const sph_grid *g, const sph_params *p,
                                  const sph_cells *cells, const float *ace_bar, float *pos_bar,
                                  float *velrho_bar, double *alpha_bar, void *ws,
                                  size_t ws_bytes, hipStream_t stream);
+
+/* Global sums of the conservation laws (Section 2: the momentum equation is
+ * evaluated pair-wise, so the internal forces of fluid pairs cancel; gravity
+ * and the boundary particles act from outside).  FP64 sums over the fluid
+ * slots [nb, n) whose cell is not SPH_EXCLUDED, with m the particle mass,
+ * x = fma(k + 1/2, cell, origin) + offset the decoded position, v the velocity
+ * of level n (velrho) and f = ace.xyz - g the internal acceleration:
+ *   out[0..2]   sum m v            linear momentum
+ *   out[3..5]   sum m f            internal force (0 for a free fluid body)
+ *   out[6]      sum m |v|^2 / 2    kinetic energy
+ *   out[7]      -sum m g . x       gravitational potential energy
+ *   out[8..10]  sum m x cross v    angular momentum about the origin
+ *   out[11..13] sum m x cross f    internal torque about the origin
+ *   out[14]     number of slots summed
+ *   out[15]     sum m |f|          scale of the internal-force sum
+ * out: [16] doubles (device).  ace: the output of sph_interact on this same
+ * state (so call it between sph_interact and sph_step), or NULL: then
+ * out[3..5], out[11..13] and out[15] are 0.  The sums run in a fixed order
+ * (block partials, then one block): bitwise reproducible for a given state.
+ * The call uses the workspace's reduction area, like sph_step: order it with
+ * the other calls sharing the workspace on one stream. */
+#define SPH_CONSERVATION_SUMS 16
+SPH_API sph_status sph_conservation(const sph_grid *g, const sph_params *p, const sph_state *st,
+                                    const float *ace, double *out, void *ws, size_t ws_bytes,
+                                    hipStream_t stream);
 
 /* Transpose of the reorder of sph_build_cells: src_bar[perm[i]] = dst_bar[i]
  * for pos_bar, velrho_bar and velrho_prev_bar (ace_bar is not used).  perm

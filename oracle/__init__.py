@@ -89,6 +89,8 @@ def lib():
         L.ora_verlet_vjp.argtypes = [C.c_int, C.c_int, dp, dp, dp, C.c_double, C.c_longlong, u8p,
                                      pp, dp, dp, dp, dp, dp, dp]
         L.ora_verlet_vjp.restype = None
+        L.ora_conservation.argtypes = [C.c_int, C.c_int, dp, dp, dp, u8p, pp, dp]
+        L.ora_conservation.restype = None
         L.ora_num_threads.argtypes = []
         L.ora_num_threads.restype = C.c_int
         _lib = L
@@ -196,6 +198,35 @@ def time_step(rho, ace, visc, nb, P, excl=None):
     excl = np.ascontiguousarray(excl, dtype=np.uint8)
     return lib().ora_dt(n, nb, _p(rho, C.c_double), _p(ace, C.c_double), _p(visc, C.c_double),
                         _p(excl, C.c_uint8), C.byref(P))
+
+
+CONSERVATION_FIELDS = ("momentum", "internal_force", "kinetic_energy", "potential_energy",
+                       "angular_momentum", "internal_torque", "count", "force_scale")
+
+
+def conservation(x, v, ace, nb, P, excl=None):
+    """Global sums of the conservation laws over the fluid (sph_oracle.c
+    ora_conservation): a [16] array, see there.  ace may be None."""
+    x = _f64(x, (-1, 3))
+    v = _f64(v, (-1, 3))
+    n = x.shape[0]
+    if excl is None:
+        excl = np.zeros(n, dtype=np.uint8)
+    excl = np.ascontiguousarray(excl, dtype=np.uint8)
+    out = np.zeros(16)
+    a4 = None if ace is None else _f64(ace, (-1, 4))
+    ap = None if a4 is None else _p(a4, C.c_double)
+    lib().ora_conservation(n, nb, _p(x, C.c_double), _p(v, C.c_double), ap, _p(excl, C.c_uint8),
+                           C.byref(P), _p(out, C.c_double))
+    return out
+
+
+def conservation_fields(out):
+    """Named views of a [16] conservation array."""
+    o = np.asarray(out, dtype=np.float64)
+    return {"momentum": o[0:3], "internal_force": o[3:6], "kinetic_energy": float(o[6]),
+            "potential_energy": float(o[7]), "angular_momentum": o[8:11],
+            "internal_torque": o[11:14], "count": float(o[14]), "force_scale": float(o[15])}
 
 
 class State:

@@ -414,6 +414,55 @@ ORA_EXPORT double ora_dt(int n, int nb, const double *rho, const double *ace, co
 }
 
 /* ------------------------------------------------------------------------ */
+/* Global sums behind the conservation laws of Section 2 (the momentum
+ * equation is evaluated pair-wise, so the internal forces of fluid pairs
+ * cancel; the boundary and gravity are the external forces).  Over the fluid
+ * particles that are not excluded, with m the particle mass, x the position,
+ * v the velocity, a the acceleration (ace, which includes gravity g) and
+ * f = a - g the internal part of it:
+ *   out[0..2]   sum m v                 linear momentum
+ *   out[3..5]   sum m f                 internal force
+ *   out[6]      sum m |v|^2 / 2         kinetic energy
+ *   out[7]      -sum m g . x            gravitational potential energy
+ *   out[8..10]  sum m x cross v         angular momentum about the origin
+ *   out[11..13] sum m x cross f         internal torque about the origin
+ *   out[14]     number of particles summed
+ *   out[15]     sum m |f|               scale of the internal-force sum
+ * Plain sequential sums in slot order.  ace may be NULL: then out[3..5],
+ * out[11..13] and out[15] are 0.  Pinned by: closed forms for a uniform
+ * translation, a rigid rotation and a resting lattice block (momentum,
+ * kinetic and potential energy, angular momentum from lattice moment sums);
+ * zero internal force and torque for pair-wise central forces on a free
+ * blob.                                                                      */
+ORA_EXPORT void ora_conservation(int n, int nb, const double *x, const double *v,
+                                 const double *ace, const uint8_t *excl, const ora_params *p,
+                                 double *out)
+{
+    for (int k = 0; k < 16; ++k) out[k] = 0.0;
+    const double m = p->mass;
+    for (int a = nb; a < n; ++a) {
+        if (excl[a]) continue;
+        const double *xa = x + 3 * (size_t)a, *va = v + 3 * (size_t)a;
+        for (int d = 0; d < 3; ++d) out[d] += m * va[d];
+        out[6] += 0.5 * m * (va[0] * va[0] + va[1] * va[1] + va[2] * va[2]);
+        out[7] -= m * (p->g[0] * xa[0] + p->g[1] * xa[1] + p->g[2] * xa[2]);
+        out[8] += m * (xa[1] * va[2] - xa[2] * va[1]);
+        out[9] += m * (xa[2] * va[0] - xa[0] * va[2]);
+        out[10] += m * (xa[0] * va[1] - xa[1] * va[0]);
+        out[14] += 1.0;
+        if (ace) {
+            const double *ac = ace + 4 * (size_t)a;
+            const double f[3] = {ac[0] - p->g[0], ac[1] - p->g[1], ac[2] - p->g[2]};
+            for (int d = 0; d < 3; ++d) out[3 + d] += m * f[d];
+            out[11] += m * (xa[1] * f[2] - xa[2] * f[1]);
+            out[12] += m * (xa[2] * f[0] - xa[0] * f[2]);
+            out[13] += m * (xa[0] * f[1] - xa[1] * f[0]);
+            out[15] += m * sqrt(f[0] * f[0] + f[1] * f[1] + f[2] * f[2]);
+        }
+    }
+}
+
+/* ------------------------------------------------------------------------ */
 /* Verlet step (Table 1, ref. [26]).  Regular step:
  *   x^{n+1} = x^n + dt v^n + dt^2/2 a^n
  *   v^{n+1} = v^{n-1} + 2 dt a^n,  rho^{n+1} = rho^{n-1} + 2 dt D^n

@@ -55,6 +55,20 @@ bool cells_ok(const sph_cells *c)
     return c && c->start && c->list && c->info;
 }
 
+bool build_args_ok(const sph_grid *g, const sph_state *src, const sph_state *dst,
+                   const sph_cells *cells, const int32_t *perm, const int32_t *dev_status)
+{
+    if (!grid_ok(g) || !state_ok(src) || !dst || !cells_ok(cells) || !dev_status) return false;
+    if (src->n > 0 && (!perm || !dst->cell || !dst->pos || !dst->velrho || !dst->velrho_prev ||
+                       !dst->id))
+        return false;
+    if (src->n > 0 && (src->cell == dst->cell || src->pos == dst->pos ||
+                       src->velrho == dst->velrho || src->velrho_prev == dst->velrho_prev ||
+                       src->id == dst->id))
+        return false;
+    return true;
+}
+
 sph_status ws_check(const sph_grid *g, int32_t n, void *ws, size_t ws_bytes, Workspace *w)
 {
     layout_workspace(g, n, nullptr, w);
@@ -106,14 +120,7 @@ sph_status sph_build_cells(const sph_grid *g, const sph_state *src, sph_state *d
                            sph_cells *cells, int32_t *perm, void *ws, size_t ws_bytes,
                            int32_t *dev_status, hipStream_t stream)
 {
-    if (!grid_ok(g) || !state_ok(src) || !dst || !cells_ok(cells) || !dev_status) return SPH_ERR_ARG;
-    if (src->n > 0 && (!perm || !dst->cell || !dst->pos || !dst->velrho || !dst->velrho_prev ||
-                       !dst->id))
-        return SPH_ERR_ARG;
-    if (src->n > 0 && (src->cell == dst->cell || src->pos == dst->pos ||
-                       src->velrho == dst->velrho || src->velrho_prev == dst->velrho_prev ||
-                       src->id == dst->id))
-        return SPH_ERR_ARG;
+    if (!build_args_ok(g, src, dst, cells, perm, dev_status)) return SPH_ERR_ARG;
     Workspace w;
     const sph_status ws_st = ws_check(g, src->n, ws, ws_bytes, &w);
     if (ws_st != SPH_OK) return ws_st;
@@ -169,6 +176,17 @@ sph_status sph_interact_backward(const sph_grid *g, const sph_params *p, const s
     if (ws_st != SPH_OK) return ws_st;
     return hip_status(launch_interact_backward(g, p, st, cells, ace_bar, pos_bar, velrho_bar,
                                                alpha_bar, w, stream));
+}
+
+sph_status sph_conservation(const sph_grid *g, const sph_params *p, const sph_state *st,
+                            const float *ace, double *out, void *ws, size_t ws_bytes,
+                            hipStream_t stream)
+{
+    if (!grid_ok(g) || !params_ok(g, p) || !state_ok(st) || !out) return SPH_ERR_ARG;
+    Workspace w;
+    const sph_status ws_st = ws_check(g, st->n, ws, ws_bytes, &w);
+    if (ws_st != SPH_OK) return ws_st;
+    return hip_status(launch_conservation(g, p, st, ace, out, w, stream));
 }
 
 sph_status sph_build_cells_backward(const int32_t *perm, int32_t n, const sph_adjoint *dst_bar,

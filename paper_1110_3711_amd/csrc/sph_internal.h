@@ -19,6 +19,7 @@ constexpr int kScanItems = 16;
 constexpr int kScanTile = kScanThreads * kScanItems;
 constexpr int kReduceThreads = 256;
 constexpr int kReduceBlocksMax = 1024;
+constexpr int kConsSums = 16;        // conservation sums (sph_conservation)
 
 inline int64_t ncell_of(const sph_grid *g)
 {
@@ -36,7 +37,8 @@ struct Workspace {
     int32_t *counters;                        // [64] work queues and flags
     int32_t *active;                          // [n] boundary cells with fluid in reach
     float *alpha_part;                        // [n] per-slot alpha adjoint
-    double *reduce;                           // [3 * kReduceBlocksMax] CFL partials
+    double *reduce;                           // [kConsSums * kReduceBlocksMax] block partials
+                                              //   (CFL maxima, conservation sums)
     size_t bytes;
 };
 
@@ -68,7 +70,7 @@ inline bool layout_workspace(const sph_grid *g, int64_t n, void *base, Workspace
     const size_t o_c = take(sizeof(int32_t) * 64);
     const size_t o_a = take(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
     const size_t o_ap = take(sizeof(float) * (size_t)(n > 0 ? n : 1));
-    const size_t o_r = take(sizeof(double) * 3 * kReduceBlocksMax);
+    const size_t o_r = take(sizeof(double) * kConsSums * kReduceBlocksMax);
     w->bytes = off;
     if (base) {
         char *b = (char *)base;
@@ -145,6 +147,8 @@ hipError_t launch_interact_backward(const sph_grid *g, const sph_params *p, cons
                                     const sph_cells *cells, const float *ace_bar, float *pos_bar,
                                     float *velrho_bar, double *alpha_bar, const Workspace &w,
                                     hipStream_t s);
+hipError_t launch_conservation(const sph_grid *g, const sph_params *p, const sph_state *st,
+                               const float *ace, double *out, const Workspace &w, hipStream_t s);
 hipError_t launch_unsort_adjoint(const int32_t *perm, int32_t n, const sph_adjoint *dst_bar,
                                  sph_adjoint *src_bar, hipStream_t s);
 hipError_t launch_step(const sph_grid *g, const sph_params *p, sph_state *st, const float *ace,

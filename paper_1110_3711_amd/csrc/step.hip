@@ -103,6 +103,127 @@ __global__ __launch_bounds__(kReduceThreads) void k_cfl_final(StepConsts C, int 
     }
 }
 
+// ---------------------------------------------------------------------------
+// Global sums of the conservation laws (Section 2), FP64, over the fluid
+// slots that are not excluded.  Fixed order: block b takes slots nb + b T + t
+// + k G T (T threads, G blocks, G fixed by n), reduces them by a tree in LDS
+// and writes kConsSums partials; one block then sums the partials in a fixed
+// tree.  Results are bitwise reproducible for a given n.
+
+struct ConsConsts {
+    double org[3];
+    double cell;
+    int32_t nc[3];
+    double g[3];
+    double mass;
+};
+
+// Per-slot terms: m v (3), m f (3), m |v|^2 / 2, -m g.x, m x cross v (3),
+// m x cross f (3), 1, m |f|, with f = a - g; the mass is applied at the end.
+__global__ __launch_bounds__(kReduceThreads) void k_cons_partial(
+    ConsConsts C, int32_t n, int32_t nb, const int32_t *__restrict__ cell,
+    const float4 *__restrict__ pos, const float4 *__restrict__ velrho,
+    const float4 *__restrict__ ace, double *__restrict__ out)
+{
+    __shared__ double sh[kConsSums][kReduceThreads];
+    double acc[kConsSums];
+#pragma unroll
+    for (int k = 0; k < kConsSums; ++k) acc[k] = 0.0;
+    for (int32_t i = nb + blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += gridDim.x * blockDim.x) {
+        const int32_t c = cell[i];
+        if (c == SPH_EXCLUDED) continue;
+        const int32_t k[3] = {c % C.nc[0], (c / C.nc[0]) % C.nc[1], c / (C.nc[0] * C.nc[1])};
+        const float4 o = pos[i];
+        const float of[3] = {o.x, o.y, o.z};
+        double x[3];
+        for (int d = 0; d < 3; ++d) x[d] = fma((double)k[d] + 0.5, C.cell, C.org[d]) + (double)of[d];
+        const float4 vr = velrho[i];
+        const double v[3] = {vr.x, vr.y, vr.z};
+        acc[0] += v[0];
+        acc[1] += v[1];
+        acc[2] += v[2];
+        acc[6] += 0.5 * (v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+        acc[7] -= C.g[0] * x[0] + C.g[1] * x[1] + C.g[2] * x[2];
+        acc[8] += x[1] * v[2] - x[2] * v[1];
+        acc[9] += x[2] * v[0] - x[0] * v[2];
+        acc[10] += x[0] * v[1] - x[1] * v[0];
+        acc[14] += 1.0;
+        if (ace) {
+            const float4 a = ace[i];
+            const double f[3] = {(double)a.x - C.g[0], (double)a.y - C.g[1], (double)a.z - C.g[2]};
+            acc[3] += f[0];
+            acc[4] += f[1];
+            acc[5] += f[2];
+            acc[11] += x[1] * f[2] - x[2] * f[1];
+            acc[12] += x[2] * f[0] - x[0] * f[2];
+            acc[13] += x[0] * f[1] - x[1] * f[0];
+            acc[15] += sqrt(f[0] * f[0] + f[1] * f[1] + f[2] * f[2]);
+        }
+    }
+    const int t = threadIdx.x;
+#pragma unroll
+    for (int k = 0; k < kConsSums; ++k) sh[k][t] = acc[k];
+    __syncthreads();
+    for (int o = kReduceThreads / 2; o > 0; o >>= 1) {
+        if (t < o) {
+#pragma unroll
+            for (int k = 0; k < kConsSums; ++k) sh[k][t] += sh[k][t + o];
+        }
+        __syncthreads();
+    }
+    if (t < kConsSums) out[(int64_t)kConsSums * blockIdx.x + t] = sh[t][0];
+}
+
+__global__ __launch_bounds__(kReduceThreads) void k_cons_final(ConsConsts C, int nblk,
+                                                              const double *__restrict__ part,
+                                                              double *__restrict__ result)
+{
+    __shared__ double sh[kConsSums][kReduceThreads];
+    const int t = threadIdx.x;
+    double acc[kConsSums];
+#pragma unroll
+    for (int k = 0; k < kConsSums; ++k) acc[k] = 0.0;
+    for (int b = t; b < nblk; b += kReduceThreads) {
+#pragma unroll
+        for (int k = 0; k < kConsSums; ++k) acc[k] += part[(int64_t)kConsSums * b + k];
+    }
+#pragma unroll
+    for (int k = 0; k < kConsSums; ++k) sh[k][t] = acc[k];
+    __syncthreads();
+    for (int o = kReduceThreads / 2; o > 0; o >>= 1) {
+        if (t < o) {
+#pragma unroll
+            for (int k = 0; k < kConsSums; ++k) sh[k][t] += sh[k][t + o];
+        }
+        __syncthreads();
+    }
+    if (t < kConsSums) result[t] = t == 14 ? sh[t][0] : C.mass * sh[t][0];
+}
+
+hipError_t launch_conservation(const sph_grid *g, const sph_params *p, const sph_state *st,
+                               const float *ace, double *out, const Workspace &w, hipStream_t s)
+{
+    ConsConsts C;
+    for (int d = 0; d < 3; ++d) {
+        C.org[d] = g->origin[d];
+        C.nc[d] = g->nc[d];
+        C.g[d] = p->g[d];
+    }
+    C.cell = g->cell;
+    C.mass = p->mass;
+    const int64_t nf = (int64_t)st->n - st->nb;
+    int nblk = (int)((nf + kReduceThreads - 1) / kReduceThreads);
+    if (nblk > kReduceBlocksMax) nblk = kReduceBlocksMax;
+    if (nblk < 1) nblk = 1;
+    k_cons_partial<<<nblk, kReduceThreads, 0, s>>>(C, st->n, st->nb, st->cell,
+                                                   (const float4 *)st->pos,
+                                                   (const float4 *)st->velrho,
+                                                   (const float4 *)ace, w.reduce);
+    k_cons_final<<<1, kReduceThreads, 0, s>>>(C, nblk, w.reduce, out);
+    return hipGetLastError();
+}
+
 __device__ inline void decode_cell(int32_t c, const int32_t *nc, int32_t &kx, int32_t &ky, int32_t &kz)
 {
     kx = c % nc[0];

@@ -22,11 +22,11 @@ SPH_DEV_OUT_OF_GRID, SPH_DEV_NONFINITE, SPH_DEV_BOUNDARY_OUT = 1, 2, 4
 SPH_FIXED_DT, SPH_ADJOINT = 1, 2
 SPH_PI_FLUID, SPH_PI_BOUNDARY, SPH_PI_ALL = 1, 2, 3
 SPH_EXCLUDED = 2**31 - 1
-ABI_VERSION = 5
+ABI_VERSION = 6
 
 EXPORTS = ["sph_workspace_bytes", "sph_ranges_bytes", "sph_abi_version", "sph_encode", "sph_decode",
            "sph_build_cells", "sph_interact", "sph_step", "sph_interact_backward",
-           "sph_build_cells_backward"]
+           "sph_build_cells_backward", "sph_conservation"]
 
 
 class Grid(C.Structure):
@@ -91,8 +91,9 @@ def load(path: str = LIB_PATH):
     L.sph_interact_backward.argtypes = [P(Grid), P(Params), P(State), P(Cells), vp, vp, vp, vp,
                                         vp, sz, vp]
     L.sph_build_cells_backward.argtypes = [vp, C.c_int32, P(Adjoint), P(Adjoint), vp]
+    L.sph_conservation.argtypes = [P(Grid), P(Params), P(State), vp, vp, vp, sz, vp]
     for f in ["sph_encode", "sph_decode", "sph_build_cells", "sph_interact", "sph_step",
-              "sph_interact_backward", "sph_build_cells_backward"]:
+              "sph_interact_backward", "sph_build_cells_backward", "sph_conservation"]:
         getattr(L, f).restype = C.c_int
     if L.sph_abi_version() != ABI_VERSION:
         raise SphError("libsph.so ABI version mismatch")
@@ -235,6 +236,21 @@ def sph_build_cells_backward(perm, n, dst_bar, src_bar, stream=None):
     _check(load().sph_build_cells_backward(_ptr(perm), int(n), C.byref(dst_bar),
                                            C.byref(src_bar), _stream(stream)),
            "sph_build_cells_backward")
+
+
+def sph_conservation(grid, params, state, ace, out, ws, stream=None):
+    import torch
+
+    _need(ace, torch.float32, 4 * state.n, "ace", optional=True)
+    _need(out, torch.float64, 16, "out")
+    _need(ws, torch.uint8, 1, "ws")
+    _check(load().sph_conservation(C.byref(grid), C.byref(params), C.byref(state), _ptr(ace),
+                                   _ptr(out), _ptr(ws), ws.numel(), _stream(stream)),
+           "sph_conservation")
+
+
+CONSERVATION_FIELDS = ("momentum", "internal_force", "kinetic_energy", "potential_energy",
+                       "angular_momentum", "internal_torque", "count", "force_scale")
 
 
 # ----------------------------------------------------------------------------
@@ -419,6 +435,19 @@ class Simulation:
         out = np.empty_like(a)
         out[ids] = a
         return out
+
+    def conservation(self, with_forces=True):
+        """FP64 conservation sums of the current state on the device
+        (sph_conservation), as a dict of named fields."""
+        import torch
+
+        out = torch.zeros(16, dtype=torch.float64, device=self.device)
+        sph_conservation(self.grid, self.params, self.a.c(), self.ace if with_forces else None,
+                         out, self.ws)
+        o = out.cpu().numpy()
+        return {"momentum": o[0:3], "internal_force": o[3:6], "kinetic_energy": float(o[6]),
+                "potential_energy": float(o[7]), "angular_momentum": o[8:11],
+                "internal_torque": o[11:14], "count": float(o[14]), "force_scale": float(o[15])}
 
     def dev_status(self) -> int:
         return int(self.status.item())

@@ -37,7 +37,7 @@ def test_library_exports_every_declared_symbol(lib):
     for name in _declared():
         assert hasattr(lib, name), name
     assert sorted(sph.EXPORTS) == _declared()
-    assert lib.sph_abi_version() == 5
+    assert lib.sph_abi_version() == 6
 
 
 def test_library_resolves_every_symbol_at_load():
