@@ -55,8 +55,9 @@
 extern "C" {
 #endif
 
-#define SPH_ABI_VERSION 6 /* 2: two-entry npairs; 3: sph_params.tensile_dp; 4: sph_cells.ranges;
-                            5: SPH_DEV_BOUNDARY_OUT; 6: sph_conservation */
+#define SPH_ABI_VERSION 7 /* 2: two-entry npairs; 3: sph_params.tensile_dp; 4: sph_cells.ranges;
+                            5: SPH_DEV_BOUNDARY_OUT; 6: sph_conservation;
+                            7: sph_state.pos64, sph_params.pos_policy */
 #define SPH_API __attribute__((visibility("default")))
 #define SPH_EXCLUDED INT32_MAX /* cell index of a particle outside the domain */
 
@@ -113,13 +114,27 @@ typedef struct {
     int32_t kernel;  /* SPH_WENDLAND5 or SPH_CUBIC_SPLINE                        */
     int32_t verlet_ns;   /* corrective Verlet step every verlet_ns steps (>= 1)  */
     int32_t bound_floor; /* 1: boundary density floored at rho0 after each step  */
-    int32_t pad_;
+    int32_t pos_policy;  /* position load of sph_interact: SPH_POS_OFFSET32 (0) or
+                          * SPH_POS_ABS64, see below                              */
     double tensile_dp;   /* tensile correction (Table 3 "tensil", ref. [34]): 0 = off;
                           * > 0: the particle spacing dp, 0 < dp < 2h.  A pair then
                           * adds (R_a + R_b) f^4, f = W(r)/W(dp), to the pressure
                           * factor of the momentum equation, with R = 0.01 P/rho^2
                           * for P > 0 and 0.2 |P|/rho^2 for P < 0.                 */
 } sph_params;
+
+/* Position-load policies of the pair kernel (sph_params.pos_policy).
+ *   SPH_POS_OFFSET32: r_ab from the FP32 offsets in the frame of the target's
+ *     cell: o_a - (o_b + (k_b - k_a) cell), the shift exact, the sum rounded
+ *     once (the default, and the only policy of the adjoint).
+ *   SPH_POS_ABS64: r_ab = fp32(x_a - x_b) from FP64 absolute positions (the
+ *     state's pos64, relative to the target cell's centre in FP64); all other
+ *     pair arithmetic is the same FP32.  A measurement variant of the forward
+ *     pair kernel with the Wendland kernel: sph_interact refuses it
+ *     (SPH_ERR_ARG) with nbr_stats, the cubic spline, the tensile correction
+ *     or a state without pos64, and sph_interact_backward refuses it. */
+#define SPH_POS_OFFSET32 0
+#define SPH_POS_ABS64 1
 
 /* Particle state (structure of arrays); one instance per side of a double
  * buffer.  All members are device arrays of length n (x4 where noted). */
@@ -131,6 +146,11 @@ typedef struct {
     float *velrho;        /* [4n] (vx, vy, vz, rho - rho0) at level n               */
     float *velrho_prev;   /* [4n] the same at level n-1 (Verlet)                     */
     int32_t *id;          /* [n] original particle id                               */
+    double *pos64;        /* optional [3n] FP64 absolute positions, or NULL.  When set:
+                             sph_encode writes x, sph_build_cells gathers it (src and dst
+                             both set, or both NULL), sph_step updates it in FP64 and
+                             re-bins (cell, offset) from it, sph_decode returns it;
+                             needed by SPH_POS_ABS64                                  */
 } sph_state;
 
 /* Output of the neighbour list (CellBeginEnd of Section 4.1, stored as one

@@ -31,6 +31,7 @@ bool params_ok(const sph_grid *g, const sph_params *p)
     if (p->gamma != 7.0) return false;
     if (p->kernel != SPH_WENDLAND5 && p->kernel != SPH_CUBIC_SPLINE) return false;
     if (p->verlet_ns < 1) return false;
+    if (p->pos_policy != SPH_POS_OFFSET32 && p->pos_policy != SPH_POS_ABS64) return false;
     if (!(p->eta2 > 0.0) || !(p->alpha >= 0.0) || !(p->cfl > 0.0)) return false;
     // tensile correction: off (0) or a spacing inside the support
     if (!(p->tensile_dp >= 0.0) || !(p->tensile_dp < 2.0 * p->h)) return false;
@@ -66,6 +67,9 @@ bool build_args_ok(const sph_grid *g, const sph_state *src, const sph_state *dst
                        src->velrho == dst->velrho || src->velrho_prev == dst->velrho_prev ||
                        src->id == dst->id))
         return false;
+    // FP64 positions are carried through when both sides hold them
+    if ((src->pos64 == nullptr) != (dst->pos64 == nullptr)) return false;
+    if (src->n > 0 && src->pos64 && src->pos64 == dst->pos64) return false;
     return true;
 }
 
@@ -135,6 +139,10 @@ sph_status sph_interact(const sph_grid *g, const sph_params *p, const sph_state 
     if (!grid_ok(g) || !params_ok(g, p) || !state_ok(st) || !cells_ok(cells)) return SPH_ERR_ARG;
     if (parts == 0 || (parts & ~SPH_PI_ALL)) return SPH_ERR_ARG;
     if (st->n > 0 && (!ace || !visc)) return SPH_ERR_ARG;
+    if (p->pos_policy == SPH_POS_ABS64 &&
+        (p->kernel != SPH_WENDLAND5 || p->tensile_dp != 0.0 || nbr_stats ||
+         (st->n > 0 && !st->pos64)))
+        return SPH_ERR_ARG;
     Workspace w;
     const sph_status ws_st = ws_check(g, st->n, ws, ws_bytes, &w);
     if (ws_st != SPH_OK) return ws_st;
@@ -170,6 +178,7 @@ sph_status sph_interact_backward(const sph_grid *g, const sph_params *p, const s
 {
     if (!grid_ok(g) || !params_ok(g, p) || !state_ok(st) || !cells_ok(cells) || !alpha_bar)
         return SPH_ERR_ARG;
+    if (p->pos_policy != SPH_POS_OFFSET32) return SPH_ERR_ARG;
     if (st->n > 0 && (!ace_bar || !pos_bar || !velrho_bar)) return SPH_ERR_ARG;
     Workspace w;
     const sph_status ws_st = ws_check(g, st->n, ws, ws_bytes, &w);

@@ -343,14 +343,18 @@ __global__ void k_range_rows(int32_t ncell, int32_t nc0, int32_t nc1, int32_t nc
 __global__ void k_gather(int32_t n, const uint32_t *__restrict__ perm,
                          const int32_t *__restrict__ cell_in, const float4 *__restrict__ pos_in,
                          const float4 *__restrict__ vr_in, const float4 *__restrict__ vp_in,
-                         const int32_t *__restrict__ id_in, int32_t *__restrict__ cell_out,
-                         float4 *__restrict__ pos_out, float4 *__restrict__ vr_out,
-                         float4 *__restrict__ vp_out, int32_t *__restrict__ id_out,
+                         const int32_t *__restrict__ id_in, const double *__restrict__ x64_in,
+                         int32_t *__restrict__ cell_out, float4 *__restrict__ pos_out,
+                         float4 *__restrict__ vr_out, float4 *__restrict__ vp_out,
+                         int32_t *__restrict__ id_out, double *__restrict__ x64_out,
                          int32_t *__restrict__ perm_out)
 {
     const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const uint32_t j = perm[i];
+    if (x64_in) {
+        for (int d = 0; d < 3; ++d) x64_out[3 * (int64_t)i + d] = x64_in[3 * (int64_t)j + d];
+    }
     cell_out[i] = cell_in[j];
     pos_out[i] = pos_in[j];
     vr_out[i] = vr_in[j];
@@ -414,8 +418,8 @@ hipError_t launch_build_cells(const sph_grid *g, const sph_state *src, sph_state
     if (n > 0)
         k_gather<<<(n + threads - 1) / threads, threads, 0, s>>>(
             n, vin, src->cell, (const float4 *)src->pos, (const float4 *)src->velrho,
-            (const float4 *)src->velrho_prev, src->id, dst->cell, (float4 *)dst->pos,
-            (float4 *)dst->velrho, (float4 *)dst->velrho_prev, dst->id, perm);
+            (const float4 *)src->velrho_prev, src->id, src->pos64, dst->cell, (float4 *)dst->pos,
+            (float4 *)dst->velrho, (float4 *)dst->velrho_prev, dst->id, dst->pos64, perm);
     return hipGetLastError();
 }
 

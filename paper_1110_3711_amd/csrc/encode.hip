@@ -26,10 +26,14 @@ __global__ void k_encode(GridD G, double rho0, double B, int32_t n, int32_t nb,
                          const double *__restrict__ v, const double *__restrict__ rho,
                          int32_t *__restrict__ cell, float4 *__restrict__ pos,
                          float4 *__restrict__ velrho, float4 *__restrict__ velrho_prev,
-                         int32_t *__restrict__ id, int32_t *__restrict__ dev_status)
+                         int32_t *__restrict__ id, double *__restrict__ pos64,
+                         int32_t *__restrict__ dev_status)
 {
     const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
+    if (pos64) {
+        for (int d = 0; d < 3; ++d) pos64[3 * (int64_t)i + d] = x[3 * (int64_t)i + d];
+    }
     bool ok = true;
     int64_t k[3];
     float o[3];
@@ -62,7 +66,8 @@ __global__ void k_encode(GridD G, double rho0, double B, int32_t n, int32_t nb,
 
 __global__ void k_decode(GridD G, double rho0, int32_t n, const int32_t *__restrict__ cell,
                          const float4 *__restrict__ pos, const float4 *__restrict__ velrho,
-                         double *__restrict__ x, double *__restrict__ v, double *__restrict__ rho)
+                         const double *__restrict__ pos64, double *__restrict__ x,
+                         double *__restrict__ v, double *__restrict__ rho)
 {
     const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -71,6 +76,8 @@ __global__ void k_decode(GridD G, double rho0, int32_t n, const int32_t *__restr
     const float4 vr = velrho[i];
     if (c == SPH_EXCLUDED) {
         x[3 * (int64_t)i] = x[3 * (int64_t)i + 1] = x[3 * (int64_t)i + 2] = __builtin_nan("");
+    } else if (pos64) {
+        for (int d = 0; d < 3; ++d) x[3 * (int64_t)i + d] = pos64[3 * (int64_t)i + d];
     } else {
         const int32_t kx = c % G.nc[0];
         const int32_t ky = (c / G.nc[0]) % G.nc[1];
@@ -94,7 +101,7 @@ hipError_t launch_encode(const sph_grid *g, const sph_params *p, const double *x
     const int blocks = (st->n + threads - 1) / threads;
     k_encode<<<blocks, threads, 0, s>>>(grid_d(g), p->rho0, B, st->n, st->nb, x, v, rho, st->cell,
                                         (float4 *)st->pos, (float4 *)st->velrho,
-                                        (float4 *)st->velrho_prev, st->id, dev_status);
+                                        (float4 *)st->velrho_prev, st->id, st->pos64, dev_status);
     return hipGetLastError();
 }
 
@@ -105,8 +112,8 @@ hipError_t launch_decode(const sph_grid *g, const sph_params *p, const sph_state
     const int threads = 256;
     const int blocks = (st->n + threads - 1) / threads;
     k_decode<<<blocks, threads, 0, s>>>(grid_d(g), p->rho0, st->n, st->cell,
-                                        (const float4 *)st->pos, (const float4 *)st->velrho, x, v,
-                                        rho);
+                                        (const float4 *)st->pos, (const float4 *)st->velrho,
+                                        st->pos64, x, v, rho);
     return hipGetLastError();
 }
 

@@ -279,6 +279,7 @@ struct PairArgs {
     const int2 *ranges;       // precomputed interaction ranges of the cells, or nullptr
     const int32_t *cell;      // cell of each slot (the frame shift of a staged candidate)
     const float4 *pos, *velrho;
+    const double *pos64;      // SPH_POS_ABS64: FP64 absolute positions [3n]
     const int32_t *ids;
     float4 *ace;        // forward: out (a, drho/dt); backward: in (abar, Dbar)
     float *visc;        // forward: out max |mu|
@@ -294,20 +295,25 @@ struct PairArgs {
 // A launch runs one work list (fluid target cells or active boundary cells),
 // or both in turn (the fused kinds: fluid cells first, then boundary cells,
 // so the short boundary items fill the tail of the launch).
-template <int KIND>
+template <int KIND, int POS = 0>
 struct KindTraits {
     static constexpr bool fused = KIND == kFwdAll || KIND == kBwdAll;
     static constexpr bool bwd = KIND == kBwdFluid || KIND == kBwdBound || KIND == kBwdAll;
     static constexpr bool fluid = KIND == kFwdFluid || KIND == kBwdFluid || fused;  // first list
-    static constexpr int tile = bwd ? 1280 : kTile;  // LDS: 32 B (forward) / 48 B per candidate
+    // LDS per candidate: 32 B (forward), 48 B (backward), 56 B (forward with
+    // FP64 positions)
+    static constexpr int tile = bwd ? 1280 : (POS ? 1024 : kTile);
     static constexpr int first = fused ? (bwd ? kBwdFluid : kFwdFluid) : KIND;
     static constexpr int second = bwd ? kBwdBound : kFwdBound;
 };
 
 // LDS of one workgroup
-template <int TILE, bool BWD, bool STATS>
+template <int TILE, bool BWD, bool STATS, int POS = 0>
 struct PairLds {
     static constexpr int STAGE = (TILE + kThreads - 1) / kThreads;
+    static constexpr int DTILE = POS ? TILE + 2 * kWave : 1;
+    double sDx[DTILE], sDy[DTILE], sDz[DTILE];  // SPH_POS_ABS64: x_b - centre of the
+                                            //   target cell, FP64, + padding
     float4 sP[TILE + 2 * kWave];            // (offset in target frame, P/rho^2) + padding
     float4 sV[TILE];                        // (v, rho - rho0)
     float4 sA[BWD ? TILE : 1];              // backward: (abar, Dbar), abar = 0 on boundary
@@ -335,12 +341,12 @@ struct LaneCtx {
 
 // One work item: the targets of cell `key` (of the list kind KIND) against
 // its stencil, staged tile by tile through the workgroup's LDS.
-template <int KIND, bool STATS, int KER, bool TENS, class L>
+template <int KIND, bool STATS, int KER, bool TENS, int POS, class L>
 __device__ __forceinline__ void pair_item(const PairConsts &K, const PairArgs &A, L &S,
                                           const LaneCtx &C, int32_t key,
                                           unsigned long long &pairs_acc)
 {
-    using T = KindTraits<KIND>;
+    using T = KindTraits<KIND, POS>;
     constexpr bool FLUID = T::fluid;
     constexpr bool BWD = T::bwd;
     constexpr int TILE = T::tile;
@@ -361,6 +367,14 @@ __device__ __forceinline__ void pair_item(const PairConsts &K, const PairArgs &A
 
     const int32_t c = FLUID ? max(key - K.ncell, 0) : min(key, K.ncell - 1);
     const int32_t cx = c % K.nc0, cy = (c / K.nc0) % K.nc1, cz = c / (K.nc0 * K.nc1);
+    // SPH_POS_ABS64: FP64 centre of the target cell; staged candidates and the
+    // targets hold x - centre in FP64, and r_ab = fp32(x_a - x_b) from those
+    double ctx = 0.0, cty = 0.0, ctz = 0.0;
+    if (POS) {
+        ctx = fma((double)cx + 0.5, K.cell64, K.org64[0]);
+        cty = fma((double)cy + 0.5, K.cell64, K.org64[1]);
+        ctz = fma((double)cz + 0.5, K.cell64, K.org64[2]);
+    }
     const int32_t tbeg = __builtin_amdgcn_readfirstlane(min(max(A.start[key], 0), K.n));
     const int32_t tend = __builtin_amdgcn_readfirstlane(min(max(A.start[key + 1], tbeg), K.n));
 
@@ -468,9 +482,21 @@ __device__ __forceinline__ void pair_item(const PairConsts &K, const PairArgs &A
             if (l >= tlen) return;
             const int slot = sBin[bin] + sCnt[u][wave][bin] + rk;
             float4 pp = A.pos[j];
-            pp.x += TENS ? sx : shift_x(j, run);
-            pp.y += R.sy[run];
-            pp.z += R.sz[run];
+            if (POS) {
+                const double dx = A.pos64[3 * (int64_t)j] - ctx;
+                const double dy = A.pos64[3 * (int64_t)j + 1] - cty;
+                const double dz = A.pos64[3 * (int64_t)j + 2] - ctz;
+                S.sDx[slot] = dx;
+                S.sDy[slot] = dy;
+                S.sDz[slot] = dz;
+                pp.x = (float)dx;
+                pp.y = (float)dy;
+                pp.z = (float)dz;
+            } else {
+                pp.x += TENS ? sx : shift_x(j, run);
+                pp.y += R.sy[run];
+                pp.z += R.sz[run];
+            }
             sP[slot] = pp;
             sV[slot] = A.velrho[j];
             if (BWD) {
@@ -485,7 +511,14 @@ __device__ __forceinline__ void pair_item(const PairConsts &K, const PairArgs &A
         if (STAGE > 1) place(1, j1, q1, bn1, rk1, sx1);
         if (STAGE > 2) place(2, j2, q2, bn2, rk2, sx2);
         if (STAGE > 3) place(3, j3, q3, bn3, rk3, sx3);
-        if (threadIdx.x < 2 * kWave) sP[tlen + threadIdx.x] = make_float4(kFar, kFar, kFar, 0.f);
+        if (threadIdx.x < 2 * kWave) {
+            sP[tlen + threadIdx.x] = make_float4(kFar, kFar, kFar, 0.f);
+            if (POS) {
+                S.sDx[tlen + threadIdx.x] = (double)kFar;
+                S.sDy[tlen + threadIdx.x] = (double)kFar;
+                S.sDz[tlen + threadIdx.x] = (double)kFar;
+            }
+        }
         __syncthreads();
 
         // ---- one wavefront per target
@@ -508,6 +541,21 @@ __device__ __forceinline__ void pair_item(const PairConsts &K, const PairArgs &A
                 pa = A.pos[a];
                 va = A.velrho[a];
                 if (BWD && FLUID) aa = A.ace[a];
+            }
+            double pax = 0.0, pay = 0.0, paz = 0.0;  // SPH_POS_ABS64 target position
+            if (POS) {
+                if (self_here) {
+                    pax = S.sDx[self_l];
+                    pay = S.sDy[self_l];
+                    paz = S.sDz[self_l];
+                } else {
+                    pax = A.pos64[3 * (int64_t)a] - ctx;
+                    pay = A.pos64[3 * (int64_t)a + 1] - cty;
+                    paz = A.pos64[3 * (int64_t)a + 2] - ctz;
+                }
+                pa.x = (float)pax;
+                pa.y = (float)pay;
+                pa.z = (float)paz;
             }
             // t = rho / rho0; the Monaghan factor cbar / rhobar for c = c0 t^3 is
             // (c0 / rho0) (ta^3 + tb^3) / (ta + tb) = (c0 / rho0) (ta^2 - ta tb + tb^2)
@@ -542,7 +590,17 @@ __device__ __forceinline__ void pair_item(const PairConsts &K, const PairArgs &A
             auto pair = [&](uint32_t off) {
                 const float4 pb = lds_load4(sPb + off);
                 const float4 vb = lds_load4(sVb + off);
-                const float rx = pa.x - pb.x, ry = pa.y - pb.y, rz = pa.z - pb.z;
+                float rx, ry, rz;
+                if (POS) {
+                    const int ix = (int)(off >> 4);
+                    rx = (float)(pax - S.sDx[ix]);
+                    ry = (float)(pay - S.sDy[ix]);
+                    rz = (float)(paz - S.sDz[ix]);
+                } else {
+                    rx = pa.x - pb.x;
+                    ry = pa.y - pb.y;
+                    rz = pa.z - pb.z;
+                }
                 const float r2 = __builtin_fmaf(rz, rz, __builtin_fmaf(ry, ry, rx * rx));
                 // the adjoint needs 1/r too: one reciprocal square root instead of
                 // a square root and a reciprocal (r = 0 only for the target itself)
@@ -664,8 +722,7 @@ __device__ __forceinline__ void pair_item(const PairConsts &K, const PairArgs &A
             // byte offsets of their staged entries, full batches of 64 are
             // evaluated at once.  The ring holds kRing entries in 256 bytes, so
             // slot k sits at rbase | (2 k mod 256).
-            auto chunk = [&](const float4 pb, int32_t cb0) {
-                const float rx = pa.x - pb.x, ry = pa.y - pb.y, rz = pa.z - pb.z;
+            auto chunk = [&](float rx, float ry, float rz, int32_t cb0) {
                 const float r2 = __builtin_fmaf(rz, rz, __builtin_fmaf(ry, ry, rx * rx));
                 const bool pass = r2 < K.rc2;
                 const unsigned long long m = ballot(pass);
@@ -693,10 +750,20 @@ __device__ __forceinline__ void pair_item(const PairConsts &K, const PairArgs &A
             const int32_t w1 = __builtin_amdgcn_readfirstlane(sBin[xbin(pa.x + K.xwin) + 1]);
             const int32_t wend = w0 + ((w1 - w0 + kWave - 1) & ~(kWave - 1));
             for (int32_t cb0 = w0; cb0 < wend; cb0 += 2 * kWave) {
-                const float4 c0 = sP[cb0 + lane];
-                const float4 c1 = sP[cb0 + kWave + lane];
-                chunk(c0, cb0);
-                if (cb0 + kWave < wend) chunk(c1, cb0 + kWave);
+                if (POS) {
+                    const int i0 = cb0 + lane, i1 = cb0 + kWave + lane;
+                    const double x0 = S.sDx[i0], y0 = S.sDy[i0], z0 = S.sDz[i0];
+                    const double x1 = S.sDx[i1], y1 = S.sDy[i1], z1 = S.sDz[i1];
+                    chunk((float)(pax - x0), (float)(pay - y0), (float)(paz - z0), cb0);
+                    if (cb0 + kWave < wend)
+                        chunk((float)(pax - x1), (float)(pay - y1), (float)(paz - z1), cb0 + kWave);
+                } else {
+                    const float4 c0 = sP[cb0 + lane];
+                    const float4 c1 = sP[cb0 + kWave + lane];
+                    chunk(pa.x - c0.x, pa.y - c0.y, pa.z - c0.z, cb0);
+                    if (cb0 + kWave < wend)
+                        chunk(pa.x - c1.x, pa.y - c1.y, pa.z - c1.z, cb0 + kWave);
+                }
             }
             if (wp > rp) {
                 __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
@@ -784,13 +851,13 @@ __device__ __forceinline__ void pair_item(const PairConsts &K, const PairArgs &A
 // (without spills); the other instantiations fit by themselves, and the
 // constraint would cost them 1-2% of scheduling freedom.  With per-pair
 // statistics the LDS allows two waves per SIMD only.
-template <int KIND, bool STATS, int KER, bool TENS>
+template <int KIND, bool STATS, int KER, bool TENS, int POS>
 __global__ __launch_bounds__(kThreads)
 __attribute__((amdgpu_waves_per_eu(TENS && !STATS ? 4 : 1, 4))) void k_interact(
     PairConsts K, PairArgs A)
 {
-    using T = KindTraits<KIND>;
-    __shared__ PairLds<T::tile, T::bwd, STATS> S;
+    using T = KindTraits<KIND, POS>;
+    __shared__ PairLds<T::tile, T::bwd, STATS, POS> S;
     LaneCtx C;
     C.lane = threadIdx.x & (kWave - 1);
     C.wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
@@ -879,11 +946,11 @@ __attribute__((amdgpu_waves_per_eu(TENS && !STATS ? 4 : 1, 4))) void k_interact(
         if (!T::fused || kind == 0) {
             const int32_t key = __builtin_amdgcn_readfirstlane(
                 min(max(A.items[ibase + item], 0), 2 * K.ncell - 1));
-            pair_item<T::first, STATS, KER, TENS>(K, A, S, C, key, p1);
+            pair_item<T::first, STATS, KER, TENS, POS>(K, A, S, C, key, p1);
         } else {
             const int32_t key =
                 __builtin_amdgcn_readfirstlane(min(max(A.items2[item], 0), 2 * K.ncell - 1));
-            pair_item<T::second, STATS, KER, TENS>(K, A, S, C, key, p2);
+            pair_item<T::second, STATS, KER, TENS, POS>(K, A, S, C, key, p2);
         }
     }
     if (A.npairs && C.lane == 0) {
@@ -1021,10 +1088,13 @@ static PairConsts pair_consts(const sph_grid *g, const sph_params *p, int32_t n)
     K.xlo = (float)(-(g->nsub + 0.5) * g->cell);
     K.xscale = (float)(kBins / ((2 * g->nsub + 1) * g->cell));
     K.xwin = (float)(2.0 * h * (1.0 + 1.0 / 1024.0));
+    K.pos_policy = p->pos_policy;
+    for (int d = 0; d < 3; ++d) K.org64[d] = g->origin[d];
+    K.cell64 = g->cell;
     return K;
 }
 
-template <int KIND, bool STATS, int KER, bool TENS>
+template <int KIND, bool STATS, int KER, bool TENS, int POS = 0>
 static hipError_t launch_one(const PairConsts &K, const PairArgs &A, hipStream_t s)
 {
     int dev = 0, cus = 0, occ = 0;
@@ -1032,11 +1102,12 @@ static hipError_t launch_one(const PairConsts &K, const PairArgs &A, hipStream_t
     if (e != hipSuccess) return e;
     e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     if (e != hipSuccess) return e;
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_interact<KIND, STATS, KER, TENS>, kThreads, 0);
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_interact<KIND, STATS, KER, TENS, POS>,
+                                                     kThreads, 0);
     if (e != hipSuccess) return e;
     if (cus <= 0) cus = 1;
     if (occ <= 0) occ = 1;
-    k_interact<KIND, STATS, KER, TENS><<<cus * occ, kThreads, 0, s>>>(K, A);
+    k_interact<KIND, STATS, KER, TENS, POS><<<cus * occ, kThreads, 0, s>>>(K, A);
     return hipGetLastError();
 }
 
@@ -1046,6 +1117,12 @@ static hipError_t launch_kind(const PairConsts &K, const PairArgs &A, bool stats
 {
     constexpr bool fwd = KIND == kFwdFluid || KIND == kFwdBound || KIND == kFwdAll;
     const bool st = fwd && stats;
+    // FP64 absolute positions (a measurement variant of the default kernel
+    // shape; the entry points refuse it with statistics, another kernel shape,
+    // the tensile correction or the adjoint)
+    if constexpr (fwd) {
+        if (K.pos_policy == SPH_POS_ABS64) return launch_one<KIND, false, SPH_WENDLAND5, false, 1>(K, A, s);
+    }
     if (K.kernel == SPH_CUBIC_SPLINE) {
         if (K.tensile)
             return st ? launch_one<KIND, fwd, SPH_CUBIC_SPLINE, true>(K, A, s)
@@ -1070,6 +1147,7 @@ static PairArgs base_args(const sph_state *st, const sph_cells *cells)
     A.cell = st->cell;
     A.pos = (const float4 *)st->pos;
     A.velrho = (const float4 *)st->velrho;
+    A.pos64 = st->pos64;
     A.ids = st->id;
     A.ace = nullptr;
     A.visc = nullptr;

@@ -129,6 +129,11 @@ struct PairConsts {
     int32_t ncell;
     int32_t n;       // particles in the state
     float xlo, xscale, xwin;  // x-bins of the staged candidates; window half-width
+    // position-load policy SPH_POS_ABS64: pair vectors from FP64 absolute
+    // positions, relative to the target cell's centre org64 + (k + 1/2) cell64
+    int32_t pos_policy;
+    double org64[3];
+    double cell64;
 };
 
 // Host launchers (one per source file).

@@ -67,6 +67,7 @@ static void alloc_state(sph_state *s, int32_t n, int32_t nb)
     s->velrho = (float *)dev(sizeof(float) * 4 * (size_t)n);
     s->velrho_prev = (float *)dev(sizeof(float) * 4 * (size_t)n);
     s->id = (int32_t *)dev(sizeof(int32_t) * (size_t)n);
+    s->pos64 = NULL; /* positions as cell + FP32 offset only */
 }
 
 int main(int argc, char **argv)

@@ -235,7 +235,7 @@ __global__ void k_verlet(StepConsts C, int32_t n, int32_t nb, int corrective,
                          const double *__restrict__ dtp, int32_t *__restrict__ cell,
                          float4 *__restrict__ pos, float4 *__restrict__ velrho,
                          float4 *__restrict__ velrho_prev, const float4 *__restrict__ ace,
-                         int32_t *__restrict__ dev_status)
+                         double *__restrict__ pos64, int32_t *__restrict__ dev_status)
 {
     const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -264,13 +264,26 @@ __global__ void k_verlet(StepConsts C, int32_t n, int32_t nb, int corrective,
     float on[3], vn[3];
     bool out = false;
     for (int d = 0; d < 3; ++d) {
-        const double u = (double)of[d] + dt * (double)vf[d] + 0.5 * dt * dt * (double)af[d];
-        const double sh = floor(u / C.cell + 0.5);
-        const int64_t kn = (int64_t)k[d] + (int64_t)sh;
-        on[d] = (float)fma(-sh, C.cell, u);
-        const double xabs = fma((double)kn + 0.5, C.cell, C.org[d]) + (double)on[d];
-        if (kn < 0 || kn >= C.nc[d] || !(xabs >= C.org[d] && xabs < C.hi[d])) out = true;
-        k[d] = (int32_t)kn;
+        if (pos64) {
+            // FP64 absolute position: update it, then bin it as sph_encode does
+            const double xn = pos64[3 * (int64_t)i + d] + dt * (double)vf[d] +
+                              0.5 * dt * dt * (double)af[d];
+            pos64[3 * (int64_t)i + d] = xn;
+            const double dd = xn - C.org[d];
+            const double kf = floor(dd / C.cell);
+            if (!(xn >= C.org[d] && xn < C.hi[d]) || kf < 0.0 || kf >= (double)C.nc[d]) out = true;
+            const int64_t kn = out ? 0 : (int64_t)kf;
+            on[d] = (float)fma(-((double)kn + 0.5), C.cell, dd);
+            k[d] = (int32_t)kn;
+        } else {
+            const double u = (double)of[d] + dt * (double)vf[d] + 0.5 * dt * dt * (double)af[d];
+            const double sh = floor(u / C.cell + 0.5);
+            const int64_t kn = (int64_t)k[d] + (int64_t)sh;
+            on[d] = (float)fma(-sh, C.cell, u);
+            const double xabs = fma((double)kn + 0.5, C.cell, C.org[d]) + (double)on[d];
+            if (kn < 0 || kn >= C.nc[d] || !(xabs >= C.org[d] && xabs < C.hi[d])) out = true;
+            k[d] = (int32_t)kn;
+        }
         vn[d] = (float)(corrective ? (double)vf[d] + dt * (double)af[d]
                                    : (double)pf[d] + 2.0 * dt * (double)af[d]);
     }
@@ -404,7 +417,7 @@ hipError_t launch_step(const sph_grid *g, const sph_params *p, sph_state *st, co
         k_verlet<<<(n + 255) / 256, 256, 0, s>>>(C, n, nb, corrective, dt, st->cell,
                                                  (float4 *)st->pos, (float4 *)st->velrho,
                                                  (float4 *)st->velrho_prev, (const float4 *)ace,
-                                                 dev_status);
+                                                 st->pos64, dev_status);
     return hipGetLastError();
 }
 

@@ -22,7 +22,8 @@ SPH_DEV_OUT_OF_GRID, SPH_DEV_NONFINITE, SPH_DEV_BOUNDARY_OUT = 1, 2, 4
 SPH_FIXED_DT, SPH_ADJOINT = 1, 2
 SPH_PI_FLUID, SPH_PI_BOUNDARY, SPH_PI_ALL = 1, 2, 3
 SPH_EXCLUDED = 2**31 - 1
-ABI_VERSION = 6
+SPH_POS_OFFSET32, SPH_POS_ABS64 = 0, 1
+ABI_VERSION = 7
 
 EXPORTS = ["sph_workspace_bytes", "sph_ranges_bytes", "sph_abi_version", "sph_encode", "sph_decode",
            "sph_build_cells", "sph_interact", "sph_step", "sph_interact_backward",
@@ -39,12 +40,13 @@ class Params(C.Structure):
                 ("c0", C.c_double), ("alpha", C.c_double), ("eta2", C.c_double),
                 ("g", C.c_double * 3), ("mass", C.c_double), ("cfl", C.c_double),
                 ("kernel", C.c_int32), ("verlet_ns", C.c_int32), ("bound_floor", C.c_int32),
-                ("pad_", C.c_int32), ("tensile_dp", C.c_double)]
+                ("pos_policy", C.c_int32), ("tensile_dp", C.c_double)]
 
 
 class State(C.Structure):
     _fields_ = [("n", C.c_int32), ("nb", C.c_int32), ("cell", C.c_void_p), ("pos", C.c_void_p),
-                ("velrho", C.c_void_p), ("velrho_prev", C.c_void_p), ("id", C.c_void_p)]
+                ("velrho", C.c_void_p), ("velrho_prev", C.c_void_p), ("id", C.c_void_p),
+                ("pos64", C.c_void_p)]
 
 
 class Cells(C.Structure):
@@ -267,8 +269,9 @@ def make_grid(origin, hi, cell, nc, nsub) -> Grid:
     return g
 
 
-def make_params(phys) -> Params:
+def make_params(phys, pos_policy: int = SPH_POS_OFFSET32) -> Params:
     p = Params()
+    p.pos_policy = int(pos_policy)
     p.h, p.rho0, p.gamma, p.c0 = phys.h, phys.rho0, phys.gamma, phys.c0
     p.alpha, p.eta2, p.mass, p.cfl = phys.alpha, phys.eta2, phys.mass, phys.cfl
     for d in range(3):
@@ -281,10 +284,12 @@ def make_params(phys) -> Params:
 class DeviceState:
     """Device arrays of one side of the double-buffered particle state."""
 
-    def __init__(self, n, nb, device):
+    def __init__(self, n, nb, device, pos64=False):
         import torch
 
         self.n, self.nb = n, nb
+        # optional FP64 absolute positions (position-load policy SPH_POS_ABS64)
+        self.pos64 = torch.empty((n, 3), dtype=torch.float64, device=device) if pos64 else None
         self.cell = torch.empty(n, dtype=torch.int32, device=device)
         self.pos = torch.empty((n, 4), dtype=torch.float32, device=device)
         self.velrho = torch.empty((n, 4), dtype=torch.float32, device=device)
@@ -300,6 +305,7 @@ class DeviceState:
             s.cell, s.pos = self.cell.data_ptr(), self.pos.data_ptr()
             s.velrho, s.velrho_prev = self.velrho.data_ptr(), self.velrho_prev.data_ptr()
             s.id = self.id.data_ptr()
+            s.pos64 = None if self.pos64 is None else self.pos64.data_ptr()
             self._c = s
         return self._c
 
@@ -312,7 +318,8 @@ class Simulation:
     the device.
     """
 
-    def __init__(self, layout, nsub: int = 1, device="cuda:0", grid=None, ranges=False):
+    def __init__(self, layout, nsub: int = 1, device="cuda:0", grid=None, ranges=False,
+                 pos64=False):
         import torch
 
         from sph_inputs import cell_grid
@@ -324,12 +331,14 @@ class Simulation:
             org, cell, nc = cell_grid(layout, nsub)
             grid = make_grid(org, layout.hi, cell, nc, nsub)
         self.grid = grid
-        self.params = make_params(layout.phys)
+        # pos64: the state keeps FP64 absolute positions and the pair kernel
+        # forms r_ab from them (SPH_POS_ABS64); otherwise cell + FP32 offset
+        self.params = make_params(layout.phys, SPH_POS_ABS64 if pos64 else SPH_POS_OFFSET32)
         n, nb = layout.n, layout.nb
         self.n, self.nb = n, nb
         self.ncell = int(grid.nc[0]) * int(grid.nc[1]) * int(grid.nc[2])
-        self.a = DeviceState(n, nb, self.device)   # current (sorted after build)
-        self.b = DeviceState(n, nb, self.device)   # scratch side
+        self.a = DeviceState(n, nb, self.device, pos64)   # current (sorted after build)
+        self.b = DeviceState(n, nb, self.device, pos64)   # scratch side
         self.ws = torch.empty(max(sph_workspace_bytes(grid, n), 1), dtype=torch.uint8,
                               device=self.device)
         if self.ws.numel() <= 1 and n > 0:

@@ -37,7 +37,7 @@ def test_library_exports_every_declared_symbol(lib):
     for name in _declared():
         assert hasattr(lib, name), name
     assert sorted(sph.EXPORTS) == _declared()
-    assert lib.sph_abi_version() == 6
+    assert lib.sph_abi_version() == 7
 
 
 def test_library_resolves_every_symbol_at_load():
@@ -173,6 +173,55 @@ def test_validation_errors_before_any_device_work(lib):
                         1 << 40, fake, None) == sph.SPH_ERR_ARG
     assert lib.sph_step(C.byref(g), C.byref(p), C.byref(st), fake, fake, fake, -1, 0, None, fake,
                         1 << 40, fake, None) == sph.SPH_ERR_ARG
+
+
+def test_position_policy_validation(lib):
+    """SPH_POS_ABS64 is a forward variant of the default kernel: the entry
+    points refuse it with per-pair statistics, the cubic spline, the tensile
+    correction, a state without pos64, in the adjoint, and refuse a reorder
+    with pos64 on one side only (no device work: fake pointers)."""
+    from paper_1110_3711_amd import sph
+    from sph_inputs import physics
+
+    g = _grid()
+    fake = C.c_void_p(16)
+    st = sph.State()
+    st.n, st.nb = 10, 0
+    st.cell = st.pos = st.velrho = st.velrho_prev = st.id = 16
+    cells = sph.Cells()
+    cells.start = cells.list = cells.info = 16
+    big = 1 << 40
+
+    def interact(p, s, stats=None):
+        return lib.sph_interact(C.byref(g), C.byref(p), C.byref(s), C.byref(cells), 3, fake, fake,
+                                None, stats, fake, big, None)
+
+    p = sph.make_params(physics(0.01), sph.SPH_POS_ABS64)
+    assert interact(p, st) == sph.SPH_ERR_ARG  # no pos64 in the state
+    st.pos64 = 64
+    for bad in ("stats", "cubic", "tensile"):
+        q = sph.make_params(physics(0.01), sph.SPH_POS_ABS64)
+        stats = None
+        if bad == "stats":
+            stats = fake
+        elif bad == "cubic":
+            q.kernel = 1
+        else:
+            q.tensile_dp = 0.01
+        assert interact(q, st, stats) == sph.SPH_ERR_ARG, bad
+    q = sph.make_params(physics(0.01), 2)  # unknown policy
+    assert interact(q, st) == sph.SPH_ERR_ARG
+    assert lib.sph_interact_backward(C.byref(g), C.byref(p), C.byref(st), C.byref(cells), fake,
+                                     fake, fake, fake, fake, big, None) == sph.SPH_ERR_ARG
+    # reorder: pos64 on both sides or on neither
+    st2 = sph.State()
+    st2.n, st2.nb = 10, 0
+    st2.cell = st2.pos = st2.velrho = st2.velrho_prev = st2.id = 32
+    assert lib.sph_build_cells(C.byref(g), C.byref(st), C.byref(st2), C.byref(cells), fake, fake,
+                               big, fake, None) == sph.SPH_ERR_ARG
+    st2.pos64 = 64  # the same array on both sides
+    assert lib.sph_build_cells(C.byref(g), C.byref(st), C.byref(st2), C.byref(cells), fake, fake,
+                               big, fake, None) == sph.SPH_ERR_ARG
 
 
 def test_product_path_has_no_cpu_fallback():

@@ -6,12 +6,16 @@ oracle to t = 0.3 s, each fluid particle refined into 8^3 children at dp/8
   65,536 fluid targets (full neighbourhoods) plus 16,384 boundary targets:
   (i)   integer cell + FP32 offset (the library's encoding), also against the
         oracle on the same encoded state;
+  (ii)  FP64 absolute positions (SPH_POS_ABS64): r_ab formed in FP64 and
+        rounded to FP32 once, the rest of the pair arithmetic as in (i);
   (iii) naive FP32 absolute positions: the layout's positions rounded to
         FP32 before encoding, which is the state a plain FP32 code holds (the
         difference of two nearby FP32 values is exact, so the pair distance
         then carries exactly the rounding of the absolute positions).
 * Step 0 (the snapshot) and step 1 (one FP64 oracle step later).
-* Neighbour-count histogram and single-step timing of the whole GPU step.
+* Neighbour-count histogram and single-step timing of the whole GPU step
+  under (i) (with and without the precomputed range table, bitwise the same
+  states) and under (ii).
 """
 
 import time
@@ -52,7 +56,7 @@ def _targets(lay, seed, nf=65536, nb=16384):
     return np.sort(np.concatenate([tb, tf])).astype(np.int32)
 
 
-def _gpu_forces(lay, x_dev, stats=False):
+def _gpu_forces(lay, x_dev, stats=False, pos64=False):
     """GPU forces (id order) of the layout with device positions from x_dev."""
     import torch
 
@@ -60,7 +64,7 @@ def _gpu_forces(lay, x_dev, stats=False):
 
     L = lay.copy()
     L.x = x_dev
-    sim = sph.Simulation(L, nsub=1)
+    sim = sph.Simulation(L, nsub=1, pos64=pos64)
     sim.build_cells()
     st = torch.zeros(2 * L.n, dtype=torch.int32, device=sim.device) if stats else None
     sim.npairs.zero_()
@@ -94,6 +98,9 @@ def _policy_errors(ora, lay, tgt, label):
                                         lay.hi)
     refq, rviscq, _, _ = ora.interact(xq, vq, rq, lay.nb, P, excl=exq, targets=tgt)
     res["i_same_state"] = _errors(ace, visc, refq, rviscq, tgt, lay.nb)
+    # (ii) FP64 absolute positions
+    ace2, visc2, _, _, _ = _gpu_forces(lay, lay.x, pos64=True)
+    res["ii_true"] = _errors(ace2, visc2, ref, rvisc, tgt, lay.nb)
     # (iii) naive FP32 absolute positions
     x32 = lay.x.astype(np.float32).astype(np.float64)
     ace3, visc3, _, _, _ = _gpu_forces(lay, x32)
@@ -105,13 +112,18 @@ def _policy_errors(ora, lay, tgt, label):
 
 
 def _assert_policies(res):
-    """(i) within the parity bar on both references; naive FP32 absolute
-    positions (iii) clearly worse than (i) against the FP64 truth."""
-    for k in ("i_true", "i_same_state"):
+    """(i) and (ii) within the parity bar; (ii), whose only position rounding
+    is that of r_ab, no worse than (i) beyond the FP32 accumulation floor
+    (2x); naive FP32 absolute positions (iii) clearly worse than (i) against
+    the FP64 truth: at least 5x in acceleration and 20x in visc (measured
+    15x and 90x)."""
+    for k in ("i_true", "i_same_state", "ii_true"):
         l2, el = res[k]
         assert max(l2) <= 1e-4 and max(el) <= 1e-3, (k, l2, el)
-    (a1, _, v1), _ = res["i_true"]
+    (a1, d1, v1), _ = res["i_true"]
+    (a2, d2, v2), _ = res["ii_true"]
     (a3, _, v3), _ = res["iii_true"]
+    assert a2 <= 2 * a1 and d2 <= 2 * d1 and v2 <= 2 * v1, (a1, a2, d1, d2, v1, v2)
     assert a3 >= 5 * a1 and v3 >= 20 * v1, (a1, a3, v1, v3)
 
 
@@ -140,18 +152,15 @@ def test_clustered_position_policies(ora, clustered):
     _assert_policies(res1)
 
 
-def test_clustered_step_timing(clustered):
-    """Whole GPU steps on the clustered layout (timing only; the state evolves
-    on the device and is not compared)."""
+def _timed_steps(lay, K=20, **opts):
     import torch
 
     from paper_1110_3711_amd import sph
 
-    sim = sph.Simulation(clustered, nsub=1)
+    sim = sph.Simulation(lay, nsub=1, **opts)
     for _ in range(3):
         sim.step()
     torch.cuda.synchronize()
-    K = 20
     npairs = torch.zeros(2, dtype=torch.int64, device=sim.device)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
@@ -163,6 +172,29 @@ def test_clustered_step_timing(clustered):
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / K
     pairs = int(npairs.sum().item()) / K
-    print(f"clustered timing: {ms:.3f} ms/step, {1e3 / ms:.1f} steps/s, {pairs:.4g} directed pairs/step, "
-          f"{pairs / ms * 1e3:.4g} pairs/s, status {sim.dev_status()}", flush=True)
+    label = ", ".join(f"{k}={v}" for k, v in opts.items()) or "default"
+    print(f"clustered timing ({label}): {ms:.3f} ms/step, {1e3 / ms:.1f} steps/s, "
+          f"{pairs:.4g} directed pairs/step, {pairs / ms * 1e3:.4g} pairs/s, "
+          f"status {sim.dev_status()}", flush=True)
     assert not sim.dev_status() & sph.SPH_DEV_NONFINITE
+    return sim
+
+
+def test_clustered_step_timing(clustered):
+    """Whole GPU steps on the clustered layout: the default path, the path
+    with the precomputed interaction ranges (Section 4.4, optimisation D),
+    which must reach bitwise the same state, and the FP64-position policy
+    (timing only)."""
+    import torch
+
+    s0 = _timed_steps(clustered)
+    a0, p0, v0 = s0.ace.clone(), s0.a.pos.clone(), s0.a.velrho.clone()
+    del s0
+    torch.cuda.empty_cache()
+    s1 = _timed_steps(clustered, ranges=True)
+    assert torch.equal(a0, s1.ace) and torch.equal(p0, s1.a.pos) and torch.equal(v0, s1.a.velrho)
+    del s1
+    torch.cuda.empty_cache()
+    s2 = _timed_steps(clustered, pos64=True)
+    del s2
+    torch.cuda.empty_cache()
