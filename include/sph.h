@@ -25,7 +25,9 @@
  *   - Every array argument is a DEVICE pointer owned by the caller; struct
  *     arguments (sph_grid, sph_params, sph_state, sph_cells) are host structs
  *     whose array members are device pointers.  The library allocates no
- *     memory and keeps no global state; it is re-entrant.
+ *     memory and keeps no global state; it is re-entrant.  (One exception,
+ *     for callers that cannot allocate: sph_build_cells_static works in a
+ *     static scratch array that each device holds, see there.)
  *   - Work is enqueued on `stream` and the call returns without
  *     synchronising.  Host-side validation returns a status immediately and
  *     enqueues nothing on failure.  Conditions found on the device are OR-ed
@@ -55,9 +57,10 @@
 extern "C" {
 #endif
 
-#define SPH_ABI_VERSION 7 /* 2: two-entry npairs; 3: sph_params.tensile_dp; 4: sph_cells.ranges;
+#define SPH_ABI_VERSION 8 /* 2: two-entry npairs; 3: sph_params.tensile_dp; 4: sph_cells.ranges;
                             5: SPH_DEV_BOUNDARY_OUT; 6: sph_conservation;
-                            7: sph_state.pos64, sph_params.pos_policy */
+                            7: sph_state.pos64, sph_params.pos_policy;
+                            8: sph_build_cells_static */
 #define SPH_API __attribute__((visibility("default")))
 #define SPH_EXCLUDED INT32_MAX /* cell index of a particle outside the domain */
 
@@ -226,6 +229,26 @@ SPH_API sph_status sph_decode(const sph_grid *g, const sph_params *p, const sph_
 SPH_API sph_status sph_build_cells(const sph_grid *g, const sph_state *src, sph_state *dst,
                            sph_cells *cells, int32_t *perm, void *ws, size_t ws_bytes,
                            int32_t *dev_status, hipStream_t stream);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * operation as sph_build_cells, same kernels and bitwise the same outputs,
+ * with the library's own scratch in place of the caller's workspace.  The
+ * scratch is one static device array of SPH_STATIC_SCRATCH_BYTES (64 MiB) per
+ * device, held from the library's load until the process ends; its device
+ * address is looked up on the first call on each device.  The call allocates
+ * nothing.  Errors: SPH_ERR_ARG as sph_build_cells; SPH_ERR_WORKSPACE (before
+ * any device call) when sph_workspace_bytes(g, src->n) exceeds the scratch,
+ * e.g. beyond about 2.4M particles on a 475,300-cell grid; SPH_ERR_HIP if the
+ * scratch address cannot be obtained or a launch fails.  All calls on one
+ * device share its scratch and every call rewrites what it reads: calls that
+ * overlap in time on one device (two streams, two threads) race and must be
+ * ordered by the caller, e.g. on one stream.  Calls on different devices are
+ * independent. */
+#define SPH_STATIC_SCRATCH_BYTES (64u << 20)
+SPH_API sph_status sph_build_cells_static(const sph_grid *g, const sph_state *src,
+                                          sph_state *dst, sph_cells *cells, int32_t *perm,
+                                          int32_t *dev_status, hipStream_t stream);
 
 /* PI (Section 2 interaction classes F-F, F-B, B-F; never B-B).  For a fluid
  * target a and every b != a within the support (r_ab^2 < 4 h^2, decided in

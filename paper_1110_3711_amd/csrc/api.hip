@@ -2,6 +2,9 @@
 // layout and the calls into the per-stage launchers.
 #include <math.h>
 
+#include <atomic>
+#include <mutex>
+
 #include "sph_internal.h"
 
 using namespace sph;
@@ -83,6 +86,38 @@ sph_status ws_check(const sph_grid *g, int32_t n, void *ws, size_t ws_bytes, Wor
 
 sph_status hip_status(hipError_t e) { return e == hipSuccess ? SPH_OK : SPH_ERR_HIP; }
 
+// The library's own scratch for callers that cannot allocate
+// (sph_build_cells_static).  Each device holds its copy of the array for the
+// life of the process.  In host code `scratch` names a host-side stand-in:
+// kernels and copies get the device address that hipGetSymbolAddress
+// returns, taken once per device with that device current.
+static __device__ __align__(256) unsigned char scratch[SPH_STATIC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+std::atomic<void *> g_scratch_ptr[kMaxDevices];
+std::mutex g_scratch_mu;
+
+hipError_t scratch_of_current_device(void **out)
+{
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    void *p = g_scratch_ptr[dev].load(std::memory_order_acquire);
+    if (!p) {
+        std::lock_guard<std::mutex> lock(g_scratch_mu);
+        p = g_scratch_ptr[dev].load(std::memory_order_relaxed);
+        if (!p) {
+            e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+            if (e != hipSuccess) return e;
+            if (!p) return hipErrorInvalidSymbol;
+            g_scratch_ptr[dev].store(p, std::memory_order_release);
+        }
+    }
+    *out = p;
+    return hipSuccess;
+}
+
 }  // namespace
 
 extern "C" {
@@ -128,6 +163,22 @@ sph_status sph_build_cells(const sph_grid *g, const sph_state *src, sph_state *d
     Workspace w;
     const sph_status ws_st = ws_check(g, src->n, ws, ws_bytes, &w);
     if (ws_st != SPH_OK) return ws_st;
+    return hip_status(launch_build_cells(g, src, dst, cells, perm, w, dev_status, stream));
+}
+
+sph_status sph_build_cells_static(const sph_grid *g, const sph_state *src, sph_state *dst,
+                                  sph_cells *cells, int32_t *perm, int32_t *dev_status,
+                                  hipStream_t stream)
+{
+    if (!build_args_ok(g, src, dst, cells, perm, dev_status)) return SPH_ERR_ARG;
+    // the size check comes before any device call
+    Workspace w;
+    layout_workspace(g, src->n, nullptr, &w);
+    if (w.bytes > (size_t)SPH_STATIC_SCRATCH_BYTES) return SPH_ERR_WORKSPACE;
+    void *base = nullptr;
+    const hipError_t e = scratch_of_current_device(&base);
+    if (e != hipSuccess) return SPH_ERR_HIP;
+    layout_workspace(g, src->n, base, &w);
     return hip_status(launch_build_cells(g, src, dst, cells, perm, w, dev_status, stream));
 }
 

@@ -23,11 +23,12 @@ SPH_FIXED_DT, SPH_ADJOINT = 1, 2
 SPH_PI_FLUID, SPH_PI_BOUNDARY, SPH_PI_ALL = 1, 2, 3
 SPH_EXCLUDED = 2**31 - 1
 SPH_POS_OFFSET32, SPH_POS_ABS64 = 0, 1
-ABI_VERSION = 7
+ABI_VERSION = 8
+STATIC_SCRATCH_BYTES = 64 << 20  # SPH_STATIC_SCRATCH_BYTES
 
 EXPORTS = ["sph_workspace_bytes", "sph_ranges_bytes", "sph_abi_version", "sph_encode", "sph_decode",
            "sph_build_cells", "sph_interact", "sph_step", "sph_interact_backward",
-           "sph_build_cells_backward", "sph_conservation"]
+           "sph_build_cells_backward", "sph_conservation", "sph_build_cells_static"]
 
 
 class Grid(C.Structure):
@@ -86,6 +87,7 @@ def load(path: str = LIB_PATH):
     L.sph_encode.argtypes = [P(Grid), P(Params), vp, vp, vp, P(State), vp, vp]
     L.sph_decode.argtypes = [P(Grid), P(Params), P(State), vp, vp, vp, vp]
     L.sph_build_cells.argtypes = [P(Grid), P(State), P(State), P(Cells), vp, vp, sz, vp, vp]
+    L.sph_build_cells_static.argtypes = [P(Grid), P(State), P(State), P(Cells), vp, vp, vp]
     L.sph_interact.argtypes = [P(Grid), P(Params), P(State), P(Cells), C.c_uint, vp, vp, vp, vp,
                                vp, sz, vp]
     L.sph_step.argtypes = [P(Grid), P(Params), P(State), vp, vp, vp, C.c_longlong, C.c_uint,
@@ -94,7 +96,8 @@ def load(path: str = LIB_PATH):
                                         vp, sz, vp]
     L.sph_build_cells_backward.argtypes = [vp, C.c_int32, P(Adjoint), P(Adjoint), vp]
     L.sph_conservation.argtypes = [P(Grid), P(Params), P(State), vp, vp, vp, sz, vp]
-    for f in ["sph_encode", "sph_decode", "sph_build_cells", "sph_interact", "sph_step",
+    for f in ["sph_encode", "sph_decode", "sph_build_cells", "sph_build_cells_static",
+              "sph_interact", "sph_step",
               "sph_interact_backward", "sph_build_cells_backward", "sph_conservation"]:
         getattr(L, f).restype = C.c_int
     if L.sph_abi_version() != ABI_VERSION:
@@ -183,6 +186,18 @@ def sph_build_cells(grid, src, dst, cells, perm, ws, dev_status, stream=None):
     _check(load().sph_build_cells(C.byref(grid), C.byref(src), C.byref(dst), C.byref(cells),
                                   _ptr(perm), _ptr(ws), ws.numel(), _ptr(dev_status),
                                   _stream(stream)), "sph_build_cells")
+
+
+def sph_build_cells_static(grid, src, dst, cells, perm, dev_status, stream=None):
+    """sph_build_cells in the library's static device scratch (no workspace
+    argument, nothing allocated)."""
+    import torch
+
+    _need(perm, torch.int32, src.n, "perm")
+    _need(dev_status, torch.int32, 1, "dev_status")
+    _check(load().sph_build_cells_static(C.byref(grid), C.byref(src), C.byref(dst),
+                                         C.byref(cells), _ptr(perm), _ptr(dev_status),
+                                         _stream(stream)), "sph_build_cells_static")
 
 
 def sph_interact(grid, params, state, cells, ace, visc, npairs, ws, nbr_stats=None,

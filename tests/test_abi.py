@@ -37,7 +37,7 @@ def test_library_exports_every_declared_symbol(lib):
     for name in _declared():
         assert hasattr(lib, name), name
     assert sorted(sph.EXPORTS) == _declared()
-    assert lib.sph_abi_version() == 7
+    assert lib.sph_abi_version() == 8
 
 
 def test_library_resolves_every_symbol_at_load():
@@ -173,6 +173,47 @@ def test_validation_errors_before_any_device_work(lib):
                         1 << 40, fake, None) == sph.SPH_ERR_ARG
     assert lib.sph_step(C.byref(g), C.byref(p), C.byref(st), fake, fake, fake, -1, 0, None, fake,
                         1 << 40, fake, None) == sph.SPH_ERR_ARG
+
+
+def test_static_scratch_entry_rejects_before_any_device_call(lib):
+    """sph_build_cells_static checks its arguments and the size of its
+    workspace against the static scratch before it touches a device (this
+    runs without one): bad arguments give SPH_ERR_ARG, a particle count whose
+    workspace exceeds the scratch gives SPH_ERR_WORKSPACE."""
+    from paper_1110_3711_amd import sph
+
+    g = _grid()
+    src, dst, cells = sph.State(), sph.State(), sph.Cells()
+    fake = C.c_void_p(16)
+    n_big = 1 << 30
+    for st, ptr in ((src, 16), (dst, 4096)):
+        st.n, st.nb = n_big, 0
+        st.cell = st.pos = st.velrho = st.velrho_prev = st.id = ptr
+    cells.start = cells.list = cells.info = 16
+    assert sph.sph_workspace_bytes(g, n_big) > sph.STATIC_SCRATCH_BYTES
+    assert lib.sph_build_cells_static(C.byref(g), C.byref(src), C.byref(dst), C.byref(cells),
+                                      fake, fake, None) == sph.SPH_ERR_WORKSPACE
+    # the largest particle count that fits this grid is accepted up to the
+    # device call (not made here); one beyond is refused
+    lo, hi = 0, n_big
+    while hi - lo > 1:
+        mid = (lo + hi) // 2
+        if sph.sph_workspace_bytes(g, mid) <= sph.STATIC_SCRATCH_BYTES:
+            lo = mid
+        else:
+            hi = mid
+    assert lo > 1_000_000
+    src.n = dst.n = hi
+    assert lib.sph_build_cells_static(C.byref(g), C.byref(src), C.byref(dst), C.byref(cells),
+                                      fake, fake, None) == sph.SPH_ERR_WORKSPACE
+    # argument errors: src and dst alias, missing dev_status, nb > n
+    assert lib.sph_build_cells_static(C.byref(g), C.byref(src), C.byref(src), C.byref(cells),
+                                      fake, fake, None) == sph.SPH_ERR_ARG
+    assert lib.sph_build_cells_static(C.byref(g), C.byref(src), C.byref(dst), C.byref(cells),
+                                      fake, None, None) == sph.SPH_ERR_ARG
+    src.nb = src.n + 1
+    assert lib.sph_build_cells_static(C.byref(g), C.byref(src), C.byref(dst), C.byref(cells),
+                                      fake, fake, None) == sph.SPH_ERR_ARG
 
 
 def test_position_policy_validation(lib):
