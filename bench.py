@@ -66,6 +66,24 @@ def _traffic_record():
     return rec.get("hbm_bytes_per_launch")
 
 
+def _host_cpu():
+    """CPU model name (from /proc/cpuinfo) and the logical CPUs this process
+    may run on."""
+    model = platform.processor() or platform.machine()
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        nproc = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        nproc = os.cpu_count()
+    return model, nproc
+
+
 def cpu_baseline(layout, budget_s: float = 12.0):
     """Time the FP64 oracle (as it stands) on the host cores: whole steps
     (interact + time step + Verlet) of the same layout."""
@@ -82,6 +100,7 @@ def cpu_baseline(layout, budget_s: float = 12.0):
         if time.perf_counter() - t0 > budget_s or steps >= 20:
             break
     dt = time.perf_counter() - t0
+    model, nproc = _host_cpu()
     return {
         "value": npairs * steps / dt,
         "unit": "pair interactions/s",
@@ -90,7 +109,8 @@ def cpu_baseline(layout, budget_s: float = 12.0):
         "kind": "oracle",
         "sample": f"{steps} whole FP64 steps (cell list, OpenMP over targets) of the same "
                   f"{layout.n:,}-particle layout; pairs/step {npairs:,} from the initial state",
-        "cpu": platform.processor() or platform.machine(),
+        "cpu": model,
+        "nproc": nproc,
     }
 
 
@@ -137,6 +157,100 @@ def adjoint_ratio(layout, steps: int, every: int, reps: int = 3):
             "peak_device_bytes": int(torch.cuda.max_memory_allocated())}
 
 
+def timed_steps(sim, K: int, warmup: int):
+    """Warm up, then time K whole steps (build_cells -> interact -> update) on
+    the current stream: HIP events around every pair stage and, on every 8th
+    step, around the whole step; inputs stay in HBM throughout."""
+    import torch
+
+    from paper_1110_3711_amd import sph
+
+    stream = torch.cuda.current_stream()
+    # warmup (also brings the dam-break state past its first steps)
+    for _ in range(warmup):
+        sim.step()
+    torch.cuda.synchronize()
+    if sim.dev_status() & sph.SPH_DEV_NONFINITE:
+        raise SystemExit("non-finite state during warmup")
+    npairs = torch.zeros(2, dtype=torch.int64, device=sim.device)  # fluid, boundary targets
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(K)]
+    # per-stage events of every 8th step (before the neighbour list, after the
+    # update): sampled, so that the extra event records barely touch the timing
+    SAMPLE = 8
+    es = {k: (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for k in range(0, K, SAMPLE)}
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record(stream)
+    t0 = time.perf_counter()
+    for k in range(K):
+        if k in es:
+            es[k][0].record(stream)
+        sim.build_cells()
+        ev[k][0].record(stream)
+        sim.interact(parts=sph.SPH_PI_ALL, npairs=npairs)
+        ev[k][1].record(stream)
+        sim.update()
+        if k in es:
+            es[k][1].record(stream)
+    stop.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    status = sim.dev_status()
+    if status & sph.SPH_DEV_NONFINITE:
+        raise SystemExit("non-finite state in the timed region")
+    return {
+        "gpu_ms": start.elapsed_time(stop),
+        "wall": wall,
+        "status": status,
+        "pi_ms": np.array([a.elapsed_time(b) for a, b in ev]),
+        "nl_ms": np.array([es[k][0].elapsed_time(ev[k][0]) for k in es]),
+        "su_ms": np.array([ev[k][1].elapsed_time(es[k][1]) for k in es]),
+        "pf": int(npairs[0].item()),
+        "pb": int(npairs[1].item()),
+    }
+
+
+def large_leg(config: str, steps: int, warmup: int):
+    """A few timed steps of the largest single-GPU layout: throughput, pair
+    kernel rate against the FP32 peak, peak device memory."""
+    import torch
+
+    from paper_1110_3711_amd import sph
+    from sph_inputs import CASES, named_case
+
+    torch.cuda.empty_cache()
+    torch.cuda.reset_peak_memory_stats()
+    lay = named_case(config)
+    sim = sph.Simulation(lay, nsub=1)
+    R = timed_steps(sim, steps, warmup)
+    pairs = R["pf"] + R["pb"]
+    t = R["gpu_ms"] / 1e3
+    flop_launch = (R["pf"] * FLOP_FLUID_PAIR + R["pb"] * FLOP_BOUND_PAIR) / steps
+    achieved = flop_launch / (R["pi_ms"].mean() / 1e3)
+    out = {
+        "workload": f"{config}: {CASES[config].description}",
+        "particles": lay.n,
+        "steps": steps,
+        "warmup": warmup,
+        "ms_per_step": R["gpu_ms"] / steps,
+        "steps_per_s": steps / t,
+        "pairs_per_s": pairs / t,
+        "pairs_per_step": pairs / steps,
+        "stage_ms": {"build_cells": float(R["nl_ms"].mean()), "interact": float(R["pi_ms"].mean()),
+                     "step": float(R["su_ms"].mean())},
+        "pair_kernel_tflops": achieved / 1e12,
+        "pair_kernel_frac": achieved / PEAK_FP32_VECTOR,
+        "peak_device_bytes": int(torch.cuda.max_memory_allocated()),
+        "dev_status": R["status"],
+    }
+    del sim
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -157,6 +271,10 @@ def main():
     ap.add_argument("--adjoint-steps", type=int, default=200)
     ap.add_argument("--adjoint-every", type=int, default=20)
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--large-config", default="dam_break_20m",
+                    help="layout of the large single-GPU leg (a few timed steps)")
+    ap.add_argument("--large-steps", type=int, default=10)
+    ap.add_argument("--no-large", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one 256 MiB device-to-device copy first (counter calibration)")
     args = ap.parse_args()
@@ -187,52 +305,11 @@ def main():
     lay = variant(named_case(args.config))
     torch.cuda.reset_peak_memory_stats()
     sim = sph.Simulation(lay, nsub=args.nsub, ranges=args.range_table)
-    stream = torch.cuda.current_stream()
-
-    # warmup (also brings the dam-break state past its first steps)
-    for _ in range(args.warmup):
-        sim.step()
-    torch.cuda.synchronize()
-    if sim.dev_status() & sph.SPH_DEV_NONFINITE:
-        raise SystemExit("non-finite state during warmup")
-
+    R = timed_steps(sim, args.steps, args.warmup)
     K = args.steps
-    npairs = torch.zeros(2, dtype=torch.int64, device=sim.device)  # fluid, boundary targets
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-          for _ in range(K)]
-    # per-stage events of every 8th step (before the neighbour list, after the
-    # update): sampled, so that the extra event records barely touch the timing
-    SAMPLE = 8
-    es = {k: (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-          for k in range(0, K, SAMPLE)}
-    start = torch.cuda.Event(enable_timing=True)
-    stop = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    start.record(stream)
-    t0 = time.perf_counter()
-    for k in range(K):
-        if k in es:
-            es[k][0].record(stream)
-        sim.build_cells()
-        ev[k][0].record(stream)
-        sim.interact(parts=sph.SPH_PI_ALL, npairs=npairs)
-        ev[k][1].record(stream)
-        sim.update()
-        if k in es:
-            es[k][1].record(stream)
-    stop.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    gpu_ms = start.elapsed_time(stop)
-    status = sim.dev_status()
-    if status & sph.SPH_DEV_NONFINITE:
-        raise SystemExit("non-finite state in the timed region")
-    pi_ms = np.array([a.elapsed_time(b) for a, b in ev])
-    nl_ms = np.array([es[k][0].elapsed_time(ev[k][0]) for k in es])
-    su_ms = np.array([ev[k][1].elapsed_time(es[k][1]) for k in es])
-    pf = int(npairs[0].item())
-    pb = int(npairs[1].item())
+    pf, pb, pi_ms, nl_ms, su_ms = R["pf"], R["pb"], R["pi_ms"], R["nl_ms"], R["su_ms"]
     pairs = pf + pb
+    gpu_ms, wall, status = R["gpu_ms"], R["wall"], R["status"]
     t = gpu_ms / 1e3
     ms_step = gpu_ms / K
 
@@ -306,9 +383,11 @@ def main():
         "paper_context": PAPER_CONTEXT,
         "roofline": roof,
     }
+    del sim
+    torch.cuda.empty_cache()
+    if not args.no_large:
+        out["large"] = large_leg(args.large_config, args.large_steps, 3)
     if not args.no_adjoint:
-        del sim
-        torch.cuda.empty_cache()
         alay = lay if args.adjoint_config == args.config else variant(named_case(args.adjoint_config))
         adj = adjoint_ratio(alay, args.adjoint_steps, args.adjoint_every)
         out["adjoint"] = adj
