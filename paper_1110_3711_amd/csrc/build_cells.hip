@@ -32,80 +32,142 @@ __device__ inline uint32_t key_of(const KeySrc &S, int64_t i)
 
 // ---------------------------------------------------------------------------
 // radix sort: per-block digit histograms, digit-major so that one exclusive
-// scan gives every (digit, block) its global output offset.
+// scan gives every (digit, block) its global output offset.  A pass sorts by
+// a digit of at most 11 bits; the key width (bit length of 2 ncell) is split
+// into the fewest such passes (two for a 20-bit key).  A block takes a tile
+// of kSortTile consecutive keys; wave w of the block takes the w-th quarter of
+// the tile, 64 keys per round, in input order.
 
-__global__ __launch_bounds__(kSortThreads) void k_radix_hist(int32_t n, int shift, KeySrc keys,
-                                                             uint32_t *__restrict__ hist,
-                                                             int nblk, int32_t *dev_status)
+// Equal-digit runs of a wave (consecutive lanes, nearly sorted input) add one
+// count per run: lanes whose left neighbour holds another digit are heads,
+// each adds the length of its run.
+__device__ inline void add_digit_runs(uint32_t *h, bool valid, uint32_t dig)
 {
-    __shared__ uint32_t h[kRadix];
-    for (int d = threadIdx.x; d < kRadix; d += kSortThreads) h[d] = 0;
+    const int lane = lane_id();
+    const uint32_t d = valid ? dig : 0xffffffffu;
+    const uint32_t dprev = __shfl_up(d, 1);
+    const bool head = valid && (lane == 0 || dprev != d);
+    const unsigned long long heads = ballot(head);
+    const unsigned long long vmask = ballot(valid);
+    if (head) {
+        const unsigned long long after = lane == 63 ? 0ull : (heads >> (lane + 1)) << (lane + 1);
+        const int end = after ? __ffsll((long long)after) - 1 : 64 - __clzll((long long)vmask);
+        atomicAdd(&h[dig], (uint32_t)(end - lane));
+    }
+}
+
+__device__ inline int64_t sort_elem(int round, int wave, int lane)
+{
+    // element of (round, wave, lane) inside the block's tile
+    return (int64_t)wave * (kSortTile / (kSortThreads / kWave)) + (int64_t)round * kWave + lane;
+}
+
+// zero (optional, first pass): a u64 array cleared on the side, grid-stride
+__global__ __launch_bounds__(kSortThreads) void k_radix_hist(int32_t n, int shift, int dbits,
+                                                             KeySrc keys,
+                                                             uint32_t *__restrict__ hist,
+                                                             int nblk, int32_t *dev_status,
+                                                             unsigned long long *__restrict__ zero,
+                                                             int64_t nzero)
+{
+    __shared__ uint32_t h[kRadixMax];
+    const int ndig = 1 << dbits;
+    const uint32_t dmask = (uint32_t)ndig - 1u;
+    for (int d = threadIdx.x; d < ndig; d += kSortThreads) h[d] = 0;
+    if (zero) {
+        for (int64_t i = (int64_t)blockIdx.x * kSortThreads + threadIdx.x; i < nzero;
+             i += (int64_t)gridDim.x * kSortThreads)
+            zero[i] = 0ull;
+    }
     __syncthreads();
+    const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
     const int64_t base = (int64_t)blockIdx.x * kSortTile;
     for (int j = 0; j < kSortItems; ++j) {
-        const int64_t e = base + (int64_t)j * kSortThreads + threadIdx.x;
-        if (e < n) {
-            atomicAdd(&h[(key_of(keys, e) >> shift) & (kRadix - 1)], 1u);
+        const int64_t e = base + sort_elem(j, wave, lane);
+        const bool valid = e < n;
+        uint32_t dig = 0;
+        if (valid) {
+            dig = (key_of(keys, e) >> shift) & dmask;
             // first pass: a boundary slot must hold a particle inside the grid
             if (!keys.keys && e < keys.nb && keys.cell[e] == SPH_EXCLUDED)
                 atomicOr(dev_status, SPH_DEV_BOUNDARY_OUT);
         }
+        add_digit_runs(h, valid, dig);
     }
     __syncthreads();
-    for (int d = threadIdx.x; d < kRadix; d += kSortThreads)
+    for (int d = threadIdx.x; d < ndig; d += kSortThreads)
         hist[(int64_t)d * nblk + blockIdx.x] = h[d];
 }
 
-// Stable scatter.  The tile is processed in kSortItems rounds of one key per
-// thread; element order inside the tile is (round, thread), i.e. ascending
-// input index.  Within a wave, equal digits are ranked with ballots; across
-// waves through per-wave digit counts in LDS; across rounds through running
-// digit counters.
+// Stable scatter.  Each wave ranks its own quarter of the tile round by round:
+// lanes with equal digits are matched with ballots, and a per-wave running
+// count per digit (LDS) gives each key its place among the wave's keys of
+// that digit.  After one barrier the per-wave counts become per-wave offsets
+// (waves in order), and every key goes to
+// global offset of (digit, block) + offset of its wave + its rank.
 __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
-    int32_t n, int shift, KeySrc keys_in, const uint32_t *__restrict__ vals_in,
+    int32_t n, int shift, int dbits, KeySrc keys_in, const uint32_t *__restrict__ vals_in,
     uint32_t *__restrict__ keys_out, uint32_t *__restrict__ vals_out,
     const uint32_t *__restrict__ offs, int nblk)
 {
     constexpr int NW = kSortThreads / kWave;
-    __shared__ uint32_t base_off[kRadix];
-    __shared__ uint32_t wcount[NW][kRadix];
+    __shared__ uint16_t wcnt[NW][kRadixMax];
+    __shared__ uint32_t sbase[kRadixMax];
+    const int ndig = 1 << dbits;
+    const uint32_t dmask = (uint32_t)ndig - 1u;
     const int t = threadIdx.x;
-    const int w = t / kWave;
-    for (int d = t; d < kRadix; d += kSortThreads) base_off[d] = offs[(int64_t)d * nblk + blockIdx.x];
+    const int wave = t / kWave, lane = t % kWave;
+    for (int d = t; d < NW * ndig; d += kSortThreads) wcnt[d / ndig][d % ndig] = 0;
+    for (int d = t; d < ndig; d += kSortThreads) sbase[d] = offs[(int64_t)d * nblk + blockIdx.x];
+    __syncthreads();
     const int64_t tile = (int64_t)blockIdx.x * kSortTile;
+    uint32_t key[kSortItems], val[kSortItems];
+    uint16_t rank[kSortItems];
+#pragma unroll
     for (int j = 0; j < kSortItems; ++j) {
-        for (int d = t; d < NW * kRadix; d += kSortThreads) (&wcount[0][0])[d] = 0;
-        __syncthreads();
-        const int64_t e = tile + (int64_t)j * kSortThreads + t;
+        const int64_t e = tile + sort_elem(j, wave, lane);
         const bool valid = e < n;
-        uint32_t key = 0, val = 0, dig = 0;
+        uint32_t k = 0, v = 0, dig = 0;
         if (valid) {
-            key = key_of(keys_in, e);
-            val = vals_in ? vals_in[e] : (uint32_t)e;  // first pass: slot index
-            dig = (key >> shift) & (kRadix - 1);
+            k = key_of(keys_in, e);
+            v = vals_in ? vals_in[e] : (uint32_t)e;  // first pass: slot index
+            dig = (k >> shift) & dmask;
         }
         unsigned long long peers = ballot(valid);
-        for (int b = 0; b < kRadixBits; ++b) {
+        for (int b = 0; b < dbits; ++b) {
             const bool bit = (dig >> b) & 1u;
             const unsigned long long m = ballot(bit);
             peers &= bit ? m : ~m;
         }
-        const unsigned rank_w = lane_rank(peers);
-        if (valid && rank_w == 0) wcount[w][dig] = (uint32_t)__popcll(peers);
-        __syncthreads();
-        if (valid) {
-            uint32_t pos = base_off[dig] + rank_w;
-            for (int ww = 0; ww < w; ++ww) pos += wcount[ww][dig];
-            keys_out[pos] = key;
-            vals_out[pos] = val;
+        const unsigned rk = lane_rank(peers);
+        uint32_t before = 0;
+        if (valid) before = wcnt[wave][dig];
+        // the wave's LDS accesses complete in order: every peer has read the
+        // count before the first peer writes it back
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        if (valid && rk == 0) wcnt[wave][dig] = (uint16_t)(before + (uint32_t)__popcll(peers));
+        key[j] = k;
+        val[j] = v;
+        rank[j] = (uint16_t)(valid ? before + rk : 0xffffu);
+    }
+    __syncthreads();
+    // per-wave counts -> offsets of each wave among the block's keys of a digit
+    for (int d = t; d < ndig; d += kSortThreads) {
+        uint32_t run = 0;
+        for (int w = 0; w < NW; ++w) {
+            const uint32_t c = wcnt[w][d];
+            wcnt[w][d] = (uint16_t)run;
+            run += c;
         }
-        __syncthreads();
-        for (int d = t; d < kRadix; d += kSortThreads) {
-            uint32_t s = 0;
-            for (int ww = 0; ww < NW; ++ww) s += wcount[ww][d];
-            base_off[d] += s;
-        }
-        __syncthreads();
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < kSortItems; ++j) {
+        if (rank[j] == 0xffffu) continue;
+        const uint32_t dig = (key[j] >> shift) & dmask;
+        const uint32_t pos = sbase[dig] + wcnt[wave][dig] + rank[j];
+        keys_out[pos] = key[j];
+        vals_out[pos] = val[j];
     }
 }
 
@@ -374,18 +436,26 @@ hipError_t launch_build_cells(const sph_grid *g, const sph_state *src, sph_state
     dst->n = src->n;
     dst->nb = src->nb;
 
-    // 1-2. radix sort over the bits of the largest key; the first pass reads
-    // the keys from the cell array and the values are the slots
+    // 1-2. radix sort over the bits of the largest key, in the fewest passes
+    // of at most kRadixBitsMax bits; the first pass reads the keys from the
+    // cell array (and clears the key counts of step 3), the values are the slots
     int bits = 0;
     while (bits < 32 && ((uint64_t)1 << bits) <= (uint64_t)(2 * (int64_t)ncell)) ++bits;
+    const int npass = (bits + kRadixBitsMax - 1) / kRadixBitsMax;
+    const int dbits = npass > 0 ? (bits + npass - 1) / npass : 0;
     uint32_t *kin = nullptr, *vin = nullptr, *kout = w.keys0, *vout = w.vals0;
     const int nblk = nblk_sort(n);
-    for (int shift = 0; shift < bits && n > 0; shift += kRadixBits) {
+    const int64_t lenks = nkeys + 1;
+    bool cleared = false;
+    for (int shift = 0; shift < bits && n > 0; shift += dbits) {
         const KeySrc ks{kin, src->cell, src->nb, ncell};
-        k_radix_hist<<<nblk, kSortThreads, 0, s>>>(n, shift, ks, w.hist, nblk, dev_status);
-        hipError_t e = exclusive_scan<uint32_t>(w.hist, (int64_t)kRadix * nblk, w.partials, s);
+        k_radix_hist<<<nblk, kSortThreads, 0, s>>>(n, shift, dbits, ks, w.hist, nblk, dev_status,
+                                                   cleared ? nullptr : w.keyscan, lenks);
+        cleared = true;
+        hipError_t e = exclusive_scan<uint32_t>(w.hist, ((int64_t)1 << dbits) * nblk, w.partials, s);
         if (e != hipSuccess) return e;
-        k_radix_scatter<<<nblk, kSortThreads, 0, s>>>(n, shift, ks, vin, kout, vout, w.hist, nblk);
+        k_radix_scatter<<<nblk, kSortThreads, 0, s>>>(n, shift, dbits, ks, vin, kout, vout, w.hist,
+                                                      nblk);
         if (kin == nullptr) {
             kin = kout;
             vin = vout;
@@ -398,8 +468,8 @@ hipError_t launch_build_cells(const sph_grid *g, const sph_state *src, sph_state
         }
     }
     // 3. key counts -> packed (count, non-empty) -> exclusive scan -> ranges
-    const int64_t lenks = nkeys + 1;
-    k_fill_u64<<<(unsigned)((lenks + threads - 1) / threads), threads, 0, s>>>(lenks, w.keyscan);
+    if (!cleared)
+        k_fill_u64<<<(unsigned)((lenks + threads - 1) / threads), threads, 0, s>>>(lenks, w.keyscan);
     if (n > 0) k_count_keys<<<(n + threads - 1) / threads, threads, 0, s>>>(n, kin, w.keyscan);
     hipError_t e = exclusive_scan<unsigned long long, true>(w.keyscan, lenks, w.partials, s);
     if (e != hipSuccess) return e;

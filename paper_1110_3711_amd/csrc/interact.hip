@@ -405,9 +405,21 @@ __device__ __forceinline__ void pair_item(const PairConsts &K, const PairArgs &A
         auto shift_x = [&](int32_t j, int run) {
             return (float)(A.cell[j] - R.cb[run]) * K.cellf;
         };
+        // Candidates farther than 2h from the target cell (box distance of
+        // their staged position) interact with none of its targets: they are
+        // neither ranked nor placed.  The margins (box half-side enlarged by
+        // 2^-20, cutoff by 2^-10) exceed the FP32 rounding of the pair test,
+        // so the kept candidates are exactly those that can pass it, in the
+        // same order: results are bitwise those of staging everything.
+        auto kept = [&](int u, const float4 p, float sx, int run) {
+            if ((int32_t)(threadIdx.x + u * kThreads) >= tlen) return false;
+            const float tx = fmaxf(fabsf(p.x + sx) - K.half, 0.f);
+            const float ty = fmaxf(fabsf(p.y + R.sy[run]) - K.half, 0.f);
+            const float tz = fmaxf(fabsf(p.z + R.sz[run]) - K.half, 0.f);
+            return __builtin_fmaf(tz, tz, __builtin_fmaf(ty, ty, tx * tx)) < K.cull2;
+        };
         // rank among the equal x-bins of this wave (stable in lane order)
-        auto rank_round = [&](int u, int bin) {
-            const bool valid = (int32_t)(threadIdx.x + u * kThreads) < tlen;
+        auto rank_round = [&](int u, int bin, bool valid) {
             unsigned long long peers = ballot(valid);
             for (int b = 0; b < kBinBits; ++b) {
                 const bool bit = (bin >> b) & 1;
@@ -436,19 +448,24 @@ __device__ __forceinline__ void pair_item(const PairConsts &K, const PairArgs &A
         if (STAGE > 1) locate(threadIdx.x + kThreads, j1, q1);
         if (STAGE > 2) locate(threadIdx.x + 2 * kThreads, j2, q2);
         if (STAGE > 3) locate(threadIdx.x + 3 * kThreads, j3, q3);
-        const float x0 = A.pos[j0].x, x1 = STAGE > 1 ? A.pos[j1].x : 0.f,
-                    x2 = STAGE > 2 ? A.pos[j2].x : 0.f, x3 = STAGE > 3 ? A.pos[j3].x : 0.f;
+        const float4 zero4 = make_float4(0.f, 0.f, 0.f, 0.f);
+        const float4 p0 = A.pos[j0], p1 = STAGE > 1 ? A.pos[j1] : zero4,
+                     p2 = STAGE > 2 ? A.pos[j2] : zero4, p3 = STAGE > 3 ? A.pos[j3] : zero4;
         const float sx0 = shift_x(j0, q0), sx1 = STAGE > 1 ? shift_x(j1, q1) : 0.f,
                     sx2 = STAGE > 2 ? shift_x(j2, q2) : 0.f, sx3 = STAGE > 3 ? shift_x(j3, q3) : 0.f;
-        const int bn0 = xbin(x0 + sx0);
-        const int bn1 = STAGE > 1 ? xbin(x1 + sx1) : 0;
-        const int bn2 = STAGE > 2 ? xbin(x2 + sx2) : 0;
-        const int bn3 = STAGE > 3 ? xbin(x3 + sx3) : 0;
+        const int bn0 = xbin(p0.x + sx0);
+        const int bn1 = STAGE > 1 ? xbin(p1.x + sx1) : 0;
+        const int bn2 = STAGE > 2 ? xbin(p2.x + sx2) : 0;
+        const int bn3 = STAGE > 3 ? xbin(p3.x + sx3) : 0;
+        const bool kp0 = kept(0, p0, sx0, q0);
+        const bool kp1 = STAGE > 1 ? kept(1, p1, sx1, q1) : false;
+        const bool kp2 = STAGE > 2 ? kept(2, p2, sx2, q2) : false;
+        const bool kp3 = STAGE > 3 ? kept(3, p3, sx3, q3) : false;
         __syncthreads();
-        const int rk0 = rank_round(0, bn0);
-        const int rk1 = STAGE > 1 ? rank_round(1, bn1) : 0;
-        const int rk2 = STAGE > 2 ? rank_round(2, bn2) : 0;
-        const int rk3 = STAGE > 3 ? rank_round(3, bn3) : 0;
+        const int rk0 = rank_round(0, bn0, kp0);
+        const int rk1 = STAGE > 1 ? rank_round(1, bn1, kp1) : 0;
+        const int rk2 = STAGE > 2 ? rank_round(2, bn2, kp2) : 0;
+        const int rk3 = STAGE > 3 ? rank_round(3, bn3, kp3) : 0;
         __syncthreads();
         if ((int)threadIdx.x < kBins) {  // per-bin offsets over (round, wave)
             const int b = threadIdx.x;
@@ -477,9 +494,9 @@ __device__ __forceinline__ void pair_item(const PairConsts &K, const PairArgs &A
         // pass B reads the candidate's cell again, except in the tensile kinds,
         // where keeping the shift of pass A leaves their 128-VGPR budget more
         // room (1.8% faster there, 0.2% slower in the default kind)
-        auto place = [&](int u, int32_t j, int run, int bin, int rk, float sx) {
+        auto place = [&](int u, int32_t j, int run, int bin, int rk, float sx, bool keep) {
             const int32_t l = threadIdx.x + u * kThreads;
-            if (l >= tlen) return;
+            if (!keep) return;
             const int slot = sBin[bin] + sCnt[u][wave][bin] + rk;
             float4 pp = A.pos[j];
             if (POS) {
@@ -507,16 +524,19 @@ __device__ __forceinline__ void pair_item(const PairConsts &K, const PairArgs &A
             if (STATS) sSlot[slot] = j;
             if (FLUID) sMap[l] = (uint16_t)slot;
         };
-        place(0, j0, q0, bn0, rk0, sx0);
-        if (STAGE > 1) place(1, j1, q1, bn1, rk1, sx1);
-        if (STAGE > 2) place(2, j2, q2, bn2, rk2, sx2);
-        if (STAGE > 3) place(3, j3, q3, bn3, rk3, sx3);
+        place(0, j0, q0, bn0, rk0, sx0, kp0);
+        if (STAGE > 1) place(1, j1, q1, bn1, rk1, sx1, kp1);
+        if (STAGE > 2) place(2, j2, q2, bn2, rk2, sx2, kp2);
+        if (STAGE > 3) place(3, j3, q3, bn3, rk3, sx3, kp3);
+        // padding after the placed candidates: the chunks of a window end
+        // before sBin[kBins] + 2 * kWave
+        const int32_t nplaced = sBin[kBins];
         if (threadIdx.x < 2 * kWave) {
-            sP[tlen + threadIdx.x] = make_float4(kFar, kFar, kFar, 0.f);
+            sP[nplaced + threadIdx.x] = make_float4(kFar, kFar, kFar, 0.f);
             if (POS) {
-                S.sDx[tlen + threadIdx.x] = (double)kFar;
-                S.sDy[tlen + threadIdx.x] = (double)kFar;
-                S.sDz[tlen + threadIdx.x] = (double)kFar;
+                S.sDx[nplaced + threadIdx.x] = (double)kFar;
+                S.sDy[nplaced + threadIdx.x] = (double)kFar;
+                S.sDz[nplaced + threadIdx.x] = (double)kFar;
             }
         }
         __syncthreads();
@@ -744,7 +764,7 @@ __device__ __forceinline__ void pair_item(const PairConsts &K, const PairArgs &A
             // are monotone in x), rounded up to whole chunks of 64; entries past
             // the window are real candidates or padding and are tested as usual.
             // Two chunks per iteration, both loaded up front: the second read
-            // ends before tlen + 2 * kWave, inside the padding.
+            // ends before sBin[kBins] + 2 * kWave, inside the padding.
             // (wave-uniform: every lane holds the same target)
             const int32_t w0 = __builtin_amdgcn_readfirstlane(sBin[xbin(pa.x - K.xwin)]);
             const int32_t w1 = __builtin_amdgcn_readfirstlane(sBin[xbin(pa.x + K.xwin) + 1]);
@@ -847,13 +867,12 @@ __device__ __forceinline__ void pair_item(const PairConsts &K, const PairArgs &A
 
 // Four waves per SIMD (two workgroups per CU) is what the LDS allows, and the
 // kernel needs them to hide its LDS and memory latency; at 129+ VGPRs only
-// three fit (about 1.6x the time).  The tensile kinds are held to 128 VGPRs
-// (without spills); the other instantiations fit by themselves, and the
-// constraint would cost them 1-2% of scheduling freedom.  With per-pair
-// statistics the LDS allows two waves per SIMD only.
+// three fit (about 1.6x the time).  Every kind without per-pair statistics is
+// held to 128 VGPRs (none spills); with statistics the LDS allows two waves
+// per SIMD only.
 template <int KIND, bool STATS, int KER, bool TENS, int POS>
 __global__ __launch_bounds__(kThreads)
-__attribute__((amdgpu_waves_per_eu(TENS && !STATS ? 4 : 1, 4))) void k_interact(
+__attribute__((amdgpu_waves_per_eu(!STATS ? 4 : 1, 4))) void k_interact(
     PairConsts K, PairArgs A)
 {
     using T = KindTraits<KIND, POS>;
@@ -1088,6 +1107,8 @@ static PairConsts pair_consts(const sph_grid *g, const sph_params *p, int32_t n)
     K.xlo = (float)(-(g->nsub + 0.5) * g->cell);
     K.xscale = (float)(kBins / ((2 * g->nsub + 1) * g->cell));
     K.xwin = (float)(2.0 * h * (1.0 + 1.0 / 1024.0));
+    K.half = (float)(0.5 * g->cell * (1.0 + ldexp(1.0, -20)));
+    K.cull2 = (float)(4.0 * h * h * (1.0 + 1.0 / 1024.0));
     K.pos_policy = p->pos_policy;
     for (int d = 0; d < 3; ++d) K.org64[d] = g->origin[d];
     K.cell64 = g->cell;

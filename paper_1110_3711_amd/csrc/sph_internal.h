@@ -9,13 +9,13 @@
 namespace sph {
 
 constexpr int kWave = 64;            // CDNA4 wavefront
-constexpr int kSortThreads = 256;    // radix sort block
+constexpr int kSortThreads = 512;    // radix sort block (8 wavefronts)
 constexpr int kSortItems = 8;        // keys per thread per block
 constexpr int kSortTile = kSortThreads * kSortItems;
-constexpr int kRadixBits = 8;
-constexpr int kRadix = 1 << kRadixBits;
+constexpr int kRadixBitsMax = 11;    // digit width of a pass: at most 11 bits
+constexpr int kRadixMax = 1 << kRadixBitsMax;
 constexpr int kScanThreads = 256;
-constexpr int kScanItems = 16;
+constexpr int kScanItems = 4;
 constexpr int kScanTile = kScanThreads * kScanItems;
 constexpr int kReduceThreads = 256;
 constexpr int kReduceBlocksMax = 1024;
@@ -31,7 +31,7 @@ inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 // Workspace layout, shared by every entry point of one simulation.
 struct Workspace {
     uint32_t *keys0, *vals0, *keys1, *vals1;  // radix ping-pong [n] each
-    uint32_t *hist;                           // [kRadix * nblk_sort]
+    uint32_t *hist;                           // [kRadixMax * nblk_sort] digit-major
     unsigned long long *partials;             // scan partial sums
     unsigned long long *keyscan;              // [nkeys + 1] packed (count << 32 | nonempty)
     int32_t *counters;                        // [64] work queues and flags
@@ -61,8 +61,8 @@ inline bool layout_workspace(const sph_grid *g, int64_t n, void *base, Workspace
     const size_t o_v0 = take(sizeof(uint32_t) * (size_t)(n > 0 ? n : 1));
     const size_t o_k1 = take(sizeof(uint32_t) * (size_t)(n > 0 ? n : 1));
     const size_t o_v1 = take(sizeof(uint32_t) * (size_t)(n > 0 ? n : 1));
-    const size_t o_h = take(sizeof(uint32_t) * (size_t)kRadix * (size_t)(nb > 0 ? nb : 1));
-    size_t np = scan_partials_needed((int64_t)kRadix * nb);
+    const size_t o_h = take(sizeof(uint32_t) * (size_t)kRadixMax * (size_t)(nb > 0 ? nb : 1));
+    size_t np = scan_partials_needed((int64_t)kRadixMax * nb);
     const size_t np2 = scan_partials_needed(nkeys + 1);
     if (np2 > np) np = np2;
     const size_t o_p = take(sizeof(unsigned long long) * np);
@@ -129,6 +129,8 @@ struct PairConsts {
     int32_t ncell;
     int32_t n;       // particles in the state
     float xlo, xscale, xwin;  // x-bins of the staged candidates; window half-width
+    float half, cull2;        // target-cell half side and squared cutoff of the staging
+                              //   box test, both enlarged to cover FP32 rounding
     // position-load policy SPH_POS_ABS64: pair vectors from FP64 absolute
     // positions, relative to the target cell's centre org64 + (k + 1/2) cell64
     int32_t pos_policy;

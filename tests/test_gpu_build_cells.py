@@ -85,6 +85,28 @@ def test_build_cells_shuffled_with_excluded(ora):
     assert np.array_equal(sim.perm.cpu().numpy(), np.arange(lay.n))
 
 
+@pytest.mark.parametrize("side_m,passes", [(0.9, 2), (6.0, 3)])
+def test_build_cells_wide_grids(ora, side_m, passes):
+    """The radix sort splits the key width (bit length of 2 ncell) into the
+    fewest passes of at most 11 bits: a 0.9 m domain of 2h-cells needs 15-bit
+    keys (two passes), a 6 m domain more than 22 bits (three passes).  The
+    particles are the 8k-fluid dam break with velocities, shuffled within the
+    boundary and the fluid ranges."""
+    from paper_1110_3711_amd import sph
+
+    lay = dam_break(0.01, 11103711 + 1, vel_sigma=0.2, vel_seed=12)
+    rng = np.random.default_rng(17)
+    perm = np.concatenate([rng.permutation(lay.nb), lay.nb + rng.permutation(lay.nf)])
+    lay.x, lay.v, lay.rho = lay.x[perm].copy(), lay.v[perm].copy(), lay.rho[perm].copy()
+    lay.hi = lay.lo + side_m
+    sim = sph.Simulation(lay, nsub=1)
+    bits = int(2 * sim.ncell).bit_length()
+    assert -(-bits // 11) == passes, (sim.ncell, bits)
+    print(f"build_cells wide grid {side_m} m: ncell={sim.ncell} ({bits}-bit keys) n={lay.n}",
+          flush=True)
+    _check(ora, lay, sim, lay.x, lay.v, lay.rho)
+
+
 def test_build_cells_empty_and_tiny(ora):
     import torch
 
