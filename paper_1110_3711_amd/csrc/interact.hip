@@ -335,7 +335,7 @@ struct PairLds {
 // the lane's first read entry and trash slot, the staged arrays
 struct LaneCtx {
     int lane, wave;
-    uint32_t rbase, rfirst, lane16, taddr, sPb, sVb, sAb;
+    uint32_t rbase, rfirst, lane16, taddr, sPb, sVb, sAb, sTb;
     XorAddr xa;
 };
 
@@ -545,18 +545,31 @@ __device__ __forceinline__ void pair_item(const PairConsts &K, const PairArgs &A
         const int32_t selfbase =
             FLUID ? __builtin_amdgcn_readfirstlane(R.vstart[R.self_run] - R.s[R.self_run]) - tb
                   : 0;
+        // LDS slot of a target staged in this tile (its staging index is
+        // selfbase + a; targets are never dropped by the staging's box
+        // test), or -1; read one target ahead, before the current target's
+        // candidate scan, to take an LDS round trip off each target's start
+        auto slot_of = [&](int32_t a) -> int32_t {
+            const int32_t v = selfbase + a;
+            return (FLUID && v >= 0 && v < tlen) ? (int32_t)sMap[v] : -1;
+        };
+        int32_t next_l = slot_of(tbeg + wave);
         for (int32_t a = tbeg + wave; a < tend; a += kWaves) {
-            const int32_t self_v = FLUID ? selfbase + a : -1;  // staging index of a
-            const bool self_here = FLUID && self_v >= 0 && self_v < tlen;
-            const int32_t self_l = self_here ? (int32_t)sMap[self_v] : 0;
+            const bool self_here = FLUID && next_l >= 0;
+            const int32_t self_l = max(next_l, 0);
+            // LDS reads through LDS addresses, global reads through global
+            // pointers, in separate (wave-uniform) branches: a select between
+            // the two pointers would turn every one of them into a flat load
             float4 pa, va, aa = make_float4(0.f, 0.f, 0.f, 0.f);
             if (self_here) {
-                pa = sP[self_l];
-                va = sV[self_l];
-                if (BWD) aa = sA[self_l];
+                const uint32_t off = (uint32_t)self_l << 4;
+                pa = lds_load4(sPb + off);
+                va = lds_load4(sVb + off);
+                if (BWD) aa = lds_load4(sAb + off);
             } else if (!FLUID && a - tbeg < kTgt) {
-                pa = S.sTgt[2 * (a - tbeg)];
-                va = S.sTgt[2 * (a - tbeg) + 1];
+                const uint32_t off = (uint32_t)(a - tbeg) << 5;
+                pa = lds_load4(C.sTb + off);
+                va = lds_load4(C.sTb + off + 16);
             } else {
                 pa = A.pos[a];
                 va = A.velrho[a];
@@ -766,8 +779,12 @@ __device__ __forceinline__ void pair_item(const PairConsts &K, const PairArgs &A
             // Two chunks per iteration, both loaded up front: the second read
             // ends before sBin[kBins] + 2 * kWave, inside the padding.
             // (wave-uniform: every lane holds the same target)
-            const int32_t w0 = __builtin_amdgcn_readfirstlane(sBin[xbin(pa.x - K.xwin)]);
-            const int32_t w1 = __builtin_amdgcn_readfirstlane(sBin[xbin(pa.x + K.xwin) + 1]);
+            // both bin starts are read before either is used (one LDS round trip)
+            const int32_t sb0 = sBin[xbin(pa.x - K.xwin)];
+            const int32_t sb1 = sBin[xbin(pa.x + K.xwin) + 1];
+            const int32_t w0 = __builtin_amdgcn_readfirstlane(sb0);
+            const int32_t w1 = __builtin_amdgcn_readfirstlane(sb1);
+            next_l = slot_of(a + kWaves);  // returns during the scan below
             const int32_t wend = w0 + ((w1 - w0 + kWave - 1) & ~(kWave - 1));
             for (int32_t cb0 = w0; cb0 < wend; cb0 += 2 * kWave) {
                 if (POS) {
@@ -892,6 +909,7 @@ __attribute__((amdgpu_waves_per_eu(!STATS ? 4 : 1, 4))) void k_interact(
     C.sPb = lds_addr(S.sP);
     C.sVb = lds_addr(S.sV);
     C.sAb = lds_addr(S.sA);
+    C.sTb = lds_addr(S.sTgt);
 
     // First list: fluid cells are list[info[0] .. info[0] + info[1]); boundary
     // cells with fluid in reach are active[0 .. nactive).  Counts are clamped
