@@ -199,9 +199,13 @@ __device__ inline float4 lds_load4(uint32_t addr)
     return make_float4(v.x, v.y, v.z, v.w);
 }
 
+// LDS byte address of a generic pointer into LDS: the low 32 bits of the
+// generic address (the shared aperture's base is 4 GiB aligned).  Unlike an
+// address-space cast this carries no null test, which the compiler would
+// otherwise re-evaluate wherever it recomputes the address.
 __device__ inline uint32_t lds_addr(const void *p)
 {
-    return (uint32_t)(uintptr_t)(const __attribute__((address_space(3))) char *)p;
+    return (uint32_t)(uintptr_t)p;
 }
 
 // ---------------------------------------------------------------------------

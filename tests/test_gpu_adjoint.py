@@ -73,21 +73,26 @@ def test_interact_backward_matches_oracle(ora, which):
     assert np.all(gx[: lay.nb, :3] == 0) and np.all(gv[: lay.nb, :3] == 0)
 
 
-def test_interact_backward_deterministic(ora):
-    """Two launches of the pair VJP on the same inputs are bitwise identical
-    (no float atomics; alpha_bar is a fixed-order FP64 sum)."""
+@pytest.mark.parametrize("which", ["dam_break_8k", "compressed"])
+def test_interact_backward_deterministic(ora, which):
+    """Three launches of the pair VJP on the same inputs are bitwise identical
+    (no float atomics; alpha_bar is a fixed-order FP64 sum).  The compressed
+    layout fills whole adjoint staging tiles with kept candidates."""
     import torch
 
     from paper_1110_3711_amd import sph
 
-    lay = dam_break(0.01, 11103711 + 1, vel_sigma=0.2, vel_seed=9)
-    print(f"interact_backward determinism n={lay.n}", flush=True)
+    if which == "compressed":
+        lay = compress(_case(dp=0.01), 0.5)
+    else:
+        lay = dam_break(0.01, 11103711 + 1, vel_sigma=0.2, vel_seed=9)
+    print(f"interact_backward determinism {which} n={lay.n}", flush=True)
     sim = sph.Simulation(lay, nsub=1)
     sim.build_cells()
     rng = np.random.default_rng(22)
     wd = torch.as_tensor(rng.normal(size=(lay.n, 4)), dtype=torch.float32, device=sim.device)
     outs = []
-    for _ in range(2):
+    for _ in range(3):
         xb = torch.zeros((lay.n, 4), dtype=torch.float32, device=sim.device)
         vb = torch.zeros((lay.n, 4), dtype=torch.float32, device=sim.device)
         ab = torch.zeros(1, dtype=torch.float64, device=sim.device)
@@ -95,8 +100,9 @@ def test_interact_backward_deterministic(ora):
                                   sim.ws)
         torch.cuda.synchronize()
         outs.append((xb, vb, ab))
-    for u, v in zip(*outs):
-        assert torch.equal(u, v)
+    for later in outs[1:]:
+        for u, v in zip(outs[0], later):
+            assert torch.equal(u, v)
 
 
 @pytest.mark.parametrize("step_index", [0, 7])
