@@ -115,6 +115,21 @@ __device__ inline unsigned wave_sum_u(unsigned v)
            (unsigned)__builtin_amdgcn_readlane((int)v, 48);
 }
 
+// Inclusive prefix sum over the 64 lanes of a wave without LDS round trips:
+// row_shr:1,2,4,8 (lanes without a source add the 0 of `old`) scan each row
+// of 16 lanes, then every row adds the totals of the rows below it.
+__device__ inline int32_t wave_scan_incl(int32_t v, int lane)
+{
+    v += __builtin_amdgcn_update_dpp(0, v, 0x111, 0xf, 0xf, false);
+    v += __builtin_amdgcn_update_dpp(0, v, 0x112, 0xf, 0xf, false);
+    v += __builtin_amdgcn_update_dpp(0, v, 0x114, 0xf, 0xf, false);
+    v += __builtin_amdgcn_update_dpp(0, v, 0x118, 0xf, 0xf, false);
+    const int32_t r0 = __builtin_amdgcn_readlane(v, 15);
+    const int32_t r1 = __builtin_amdgcn_readlane(v, 31);
+    const int32_t r2 = __builtin_amdgcn_readlane(v, 47);
+    return v + (lane >= 16 ? r0 : 0) + (lane >= 32 ? r1 : 0) + (lane >= 48 ? r2 : 0);
+}
+
 // one exchange step of a transposed reduction: lanes with the bit clear keep lo
 // and add the partner's lo, lanes with the bit set keep hi and add the
 // partner's hi, so the number of live values halves while each covers twice
@@ -256,11 +271,7 @@ __device__ void build_runs(const PairConsts &K, const int32_t *__restrict__ star
     // inclusive scan of the run lengths over the first wavefront (nr <= 50)
     if (threadIdx.x < kWave) {
         const int lane = threadIdx.x;
-        int32_t v = len;
-        for (int o = 1; o < kWave; o <<= 1) {
-            const int32_t u = __shfl_up(v, o);
-            if (lane >= o) v += u;
-        }
+        const int32_t v = wave_scan_incl(len, lane);
         if (lane < nr) R.vstart[lane + 1] = v;
         if (lane == 0) R.vstart[0] = 0;
         if (lane == nr - 1) {
@@ -471,27 +482,31 @@ __device__ __forceinline__ void pair_item(const PairConsts &K, const PairArgs &A
         const int rk2 = STAGE > 2 ? rank_round(2, bn2, kp2) : 0;
         const int rk3 = STAGE > 3 ? rank_round(3, bn3, kp3) : 0;
         __syncthreads();
-        if ((int)threadIdx.x < kBins) {  // per-bin offsets over (round, wave)
+        // per-bin offsets over (round, wave), then the bin starts (exclusive
+        // scan of the bin totals), both in the first wavefront; the counts are
+        // read eight at a time ahead of their running sums (four LDS round
+        // trips per bin instead of one per count)
+        static_assert(kBins <= kWave, "one lane per x-bin");
+        if (threadIdx.x < kWave) {
             const int b = threadIdx.x;
-            int run = 0;
-            for (int u = 0; u < STAGE; ++u)
-                for (int w = 0; w < kWaves; ++w) {
-                    const int cc = sCnt[u][w][b];
-                    sCnt[u][w][b] = (uint16_t)run;
-                    run += cc;
+            int32_t run = 0;
+            if (b < kBins) {
+                uint16_t *const cnt = &sCnt[0][0][0];
+#pragma unroll
+                for (int k0 = 0; k0 < STAGE * kWaves; k0 += 8) {
+                    uint16_t cc[8];
+#pragma unroll
+                    for (int k = 0; k < 8; ++k) cc[k] = cnt[(k0 + k) * kBins + b];
+#pragma unroll
+                    for (int k = 0; k < 8; ++k) {
+                        cnt[(k0 + k) * kBins + b] = (uint16_t)run;
+                        run += cc[k];
+                    }
                 }
-            sBin[b + 1] = run;
-        }
-        __syncthreads();
-        if (threadIdx.x < kWave) {  // bin starts: exclusive scan of the bin totals
-            const int ln = threadIdx.x;
-            int32_t v = ln < kBins ? sBin[ln + 1] : 0;
-            for (int o = 1; o < kWave; o <<= 1) {
-                const int32_t t = __shfl_up(v, o);
-                if (ln >= o) v += t;
             }
-            if (ln < kBins) sBin[ln + 1] = v;
-            if (ln == 0) sBin[0] = 0;
+            const int32_t v = wave_scan_incl(run, b);
+            if (b < kBins) sBin[b + 1] = v;
+            if (b == 0) sBin[0] = 0;
         }
         __syncthreads();
         // pass B: write each candidate to its sorted slot
