@@ -198,7 +198,7 @@ def timed_steps(sim, K: int, warmup: int):
     stop.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    status = sim.dev_status()
+    status = sim.check_status()
     if status & sph.SPH_DEV_NONFINITE:
         raise SystemExit("non-finite state in the timed region")
     return {

@@ -38,13 +38,14 @@ __device__ inline uint32_t key_of(const KeySrc &S, int64_t i)
 // of kSortTile consecutive keys; wave w of the block takes the w-th quarter of
 // the tile, 64 keys per round, in input order.
 
-// Equal-digit runs of a wave (consecutive lanes, nearly sorted input) add one
-// count per run: lanes whose left neighbour holds another digit are heads,
-// each adds the length of its run.
-__device__ inline void add_digit_runs(uint32_t *h, bool valid, uint32_t dig)
+// Runs of equal values in a wave (consecutive lanes, nearly sorted input) are
+// counted once: lanes whose left neighbour holds another value are heads, and
+// each head adds the length of its run through add(value, length).
+template <class Add>
+__device__ inline void add_runs(bool valid, uint32_t val, Add &&add)
 {
     const int lane = lane_id();
-    const uint32_t d = valid ? dig : 0xffffffffu;
+    const uint32_t d = valid ? val : 0xffffffffu;
     const uint32_t dprev = __shfl_up(d, 1);
     const bool head = valid && (lane == 0 || dprev != d);
     const unsigned long long heads = ballot(head);
@@ -52,8 +53,13 @@ __device__ inline void add_digit_runs(uint32_t *h, bool valid, uint32_t dig)
     if (head) {
         const unsigned long long after = lane == 63 ? 0ull : (heads >> (lane + 1)) << (lane + 1);
         const int end = after ? __ffsll((long long)after) - 1 : 64 - __clzll((long long)vmask);
-        atomicAdd(&h[dig], (uint32_t)(end - lane));
+        add(val, (uint32_t)(end - lane));
     }
+}
+
+__device__ inline void add_digit_runs(uint32_t *h, bool valid, uint32_t dig)
+{
+    add_runs(valid, dig, [&](uint32_t d, uint32_t c) { atomicAdd(&h[d], c); });
 }
 
 __device__ inline int64_t sort_elem(int round, int wave, int lane)
@@ -105,10 +111,13 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_hist(int32_t n, int shif
 // that digit.  After one barrier the per-wave counts become per-wave offsets
 // (waves in order), and every key goes to
 // global offset of (digit, block) + offset of its wave + its rank.
+// counts (last pass): every key is also counted, ks[key] += count << 32, one
+// atomic per run of equal keys in a wave (the input of the last pass is
+// sorted by the lower digits, so a cell's keys arrive together).
 __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
     int32_t n, int shift, int dbits, KeySrc keys_in, const uint32_t *__restrict__ vals_in,
     uint32_t *__restrict__ keys_out, uint32_t *__restrict__ vals_out,
-    const uint32_t *__restrict__ offs, int nblk)
+    const uint32_t *__restrict__ offs, int nblk, unsigned long long *__restrict__ counts)
 {
     constexpr int NW = kSortThreads / kWave;
     __shared__ uint16_t wcnt[NW][kRadixMax];
@@ -140,6 +149,10 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
             peers &= bit ? m : ~m;
         }
         const unsigned rk = lane_rank(peers);
+        if (counts)
+            add_runs(valid, k, [&](uint32_t key, uint32_t c) {
+                atomicAdd(&counts[key], (unsigned long long)c << 32);
+            });
         uint32_t before = 0;
         if (valid) before = wcnt[wave][dig];
         // the wave's LDS accesses complete in order: every peer has read the
@@ -203,11 +216,14 @@ __device__ inline T scan_load(const T *a, int64_t e, int64_t len)
     return MARK ? (v ? (T)(v | (T)1) : (T)0) : v;
 }
 
+// zero1 (optional): one int cleared on the side
 template <typename T, bool MARK>
 __global__ __launch_bounds__(kScanThreads) void k_scan_reduce(int64_t len, const T *__restrict__ a,
-                                                              unsigned long long *__restrict__ part)
+                                                              unsigned long long *__restrict__ part,
+                                                              int32_t *__restrict__ zero1)
 {
     __shared__ T sh[kScanThreads];
+    if (zero1 && blockIdx.x == 0 && threadIdx.x == 0) *zero1 = 0;
     const int64_t base = (int64_t)blockIdx.x * kScanTile;
     T s = 0;
     for (int j = 0; j < kScanItems; ++j)
@@ -296,7 +312,7 @@ static hipError_t exclusive_scan(T *a, int64_t len, unsigned long long *part, hi
 {
     if (len <= 0) return hipSuccess;
     const int64_t nblk = (len + kScanTile - 1) / kScanTile;
-    k_scan_reduce<T, MARK><<<(unsigned)nblk, kScanThreads, 0, s>>>(len, a, part);
+    k_scan_reduce<T, MARK><<<(unsigned)nblk, kScanThreads, 0, s>>>(len, a, part, nullptr);
     if (nblk <= kScanFusedTiles) {
         k_scan_apply<T, MARK, true><<<(unsigned)nblk, kScanThreads, 0, s>>>(len, a, part);
     } else {
@@ -315,53 +331,66 @@ __global__ void k_fill_u64(int64_t len, unsigned long long *__restrict__ a)
     if (i < len) a[i] = 0ull;
 }
 
-// Count keys, one atomic per run of equal keys inside a wave.
-__global__ void k_count_keys(int32_t n, const uint32_t *__restrict__ keys,
-                             unsigned long long *__restrict__ ks)
+// Cell ranges from the key counts: the apply step of the exclusive scan of
+// the packed counts (count << 32 | non-empty mark), written out at once.  For
+// key k the exclusive prefix is (first slot of k) << 32 | (number of non-empty
+// keys before k): start[k] gets the first, a non-empty key gets list slot of
+// the second; info[1] (fluid cells) is li(2 ncell) - li(ncell), added up by
+// the two blocks holding those keys (the reduce step cleared it).
+template <bool PREFIX>
+__global__ __launch_bounds__(kScanThreads) void k_scan_emit(
+    int64_t nkeys, int32_t n, int32_t ncell, const unsigned long long *__restrict__ ks,
+    const unsigned long long *__restrict__ part, int32_t *__restrict__ start,
+    int32_t *__restrict__ list, int32_t *__restrict__ info)
 {
-    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    const bool valid = i < n;
-    const uint32_t k = valid ? keys[i] : 0xffffffffu;
-    const uint32_t kprev = __shfl_up(k, 1);
-    const int lane = lane_id();
-    const bool head = valid && (lane == 0 || kprev != k);
-    const unsigned long long heads = ballot(head);
-    const unsigned long long vmask = ballot(valid);
-    if (head) {
-        // run length: up to the next head in this wave or the end of valid lanes
-        const unsigned long long after = lane == 63 ? 0ull : (heads >> (lane + 1)) << (lane + 1);
-        int end;
-        if (after) end = __ffsll((long long)after) - 1;
-        else end = 64 - __clzll((long long)vmask);
-        atomicAdd(&ks[k], ((unsigned long long)(end - lane)) << 32);
+    using T = unsigned long long;
+    __shared__ T sh[kScanThreads];
+    __shared__ T sp[kScanThreads];
+    const int64_t len = nkeys + 1;
+    T base;
+    if (PREFIX) {
+        T pre = 0;
+        for (int64_t i = threadIdx.x; i < (int64_t)blockIdx.x; i += kScanThreads) pre += part[i];
+        sp[threadIdx.x] = pre;
+        __syncthreads();
+        for (int o = kScanThreads / 2; o > 0; o >>= 1) {
+            if ((int)threadIdx.x < o) sp[threadIdx.x] += sp[threadIdx.x + o];
+            __syncthreads();
+        }
+        base = sp[0];
+    } else {
+        base = part[blockIdx.x];
     }
-}
-
-// After the exclusive scan (with the non-empty mark), ks[k] = (first slot of
-// key k) << 32 | (number of non-empty keys before k).
-__global__ void k_emit_ranges(int64_t nkeys, int32_t n, int32_t ncell,
-                              const unsigned long long *__restrict__ ks,
-                              int32_t *__restrict__ start, int32_t *__restrict__ list,
-                              int32_t *__restrict__ info)
-{
-    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k > nkeys) return;
-    const unsigned long long v = ks[k];
-    const int32_t st = (int32_t)(v >> 32);
-    start[k] = st;
-    if (k == nkeys) {
-        // ks[nkeys] = totals: all particles, all non-empty keys
-        return;
+    const int64_t first = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+    T raw[kScanItems], loc[kScanItems];
+    T s = 0;
+    for (int j = 0; j < kScanItems; ++j) {
+        raw[j] = first + j < len ? ks[first + j] : 0ull;
+        loc[j] = scan_load<T, true>(ks, first + j, len);
+        s += loc[j];
     }
-    const unsigned long long vn = ks[k + 1];
-    const int32_t cnt = (int32_t)(vn >> 32) - st;
-    const int32_t li = (int32_t)(v & 0xffffffffull);
-    if (cnt > 0 && k < 2 * (int64_t)ncell) list[li] = (int32_t)k;
-    if (k == ncell) info[0] = li;                          // boundary cells
-    if (k == 2 * (int64_t)ncell) {
-        info[1] = li - (int32_t)(ks[ncell] & 0xffffffffull);  // fluid cells
-        info[2] = n - st;                                   // excluded particles
-        info[3] = 0;
+    T tot;
+    const T ex = block_exclusive_scan<T>(s, sh, &tot);
+    T run = base + ex;
+    for (int j = 0; j < kScanItems; ++j) {
+        const int64_t k = first + j;
+        if (k > nkeys) break;
+        const int32_t st = (int32_t)(run >> 32);
+        const int32_t li = (int32_t)(run & 0xffffffffull);
+        start[k] = st;
+        if (k < nkeys) {
+            if ((raw[j] >> 32) > 0 && k < 2 * (int64_t)ncell) list[li] = (int32_t)k;
+            if (k == ncell) {
+                info[0] = li;                  // boundary cells
+                atomicAdd(&info[1], -li);
+            }
+            if (k == 2 * (int64_t)ncell) {
+                atomicAdd(&info[1], li);       // fluid cells
+                info[2] = n - st;              // excluded particles
+                info[3] = 0;
+            }
+        }
+        run += loc[j];
     }
 }
 
@@ -454,8 +483,9 @@ hipError_t launch_build_cells(const sph_grid *g, const sph_state *src, sph_state
         cleared = true;
         hipError_t e = exclusive_scan<uint32_t>(w.hist, ((int64_t)1 << dbits) * nblk, w.partials, s);
         if (e != hipSuccess) return e;
+        const bool last = shift + dbits >= bits;
         k_radix_scatter<<<nblk, kSortThreads, 0, s>>>(n, shift, dbits, ks, vin, kout, vout, w.hist,
-                                                      nblk);
+                                                      nblk, last ? w.keyscan : nullptr);
         if (kin == nullptr) {
             kin = kout;
             vin = vout;
@@ -467,14 +497,23 @@ hipError_t launch_build_cells(const sph_grid *g, const sph_state *src, sph_state
             t = vin; vin = vout; vout = t;
         }
     }
-    // 3. key counts -> packed (count, non-empty) -> exclusive scan -> ranges
+    // 3. key counts (taken by the last pass) -> exclusive scan of the packed
+    //    (count, non-empty) values, whose apply step writes the ranges
     if (!cleared)
         k_fill_u64<<<(unsigned)((lenks + threads - 1) / threads), threads, 0, s>>>(lenks, w.keyscan);
-    if (n > 0) k_count_keys<<<(n + threads - 1) / threads, threads, 0, s>>>(n, kin, w.keyscan);
-    hipError_t e = exclusive_scan<unsigned long long, true>(w.keyscan, lenks, w.partials, s);
-    if (e != hipSuccess) return e;
-    k_emit_ranges<<<(unsigned)((lenks + threads - 1) / threads), threads, 0, s>>>(
-        nkeys, n, ncell, w.keyscan, cells->start, cells->list, cells->info);
+    {
+        const int64_t nts = (lenks + kScanTile - 1) / kScanTile;
+        k_scan_reduce<unsigned long long, true><<<(unsigned)nts, kScanThreads, 0, s>>>(
+            lenks, w.keyscan, w.partials, cells->info + 1);
+        if (nts <= kScanFusedTiles) {
+            k_scan_emit<true><<<(unsigned)nts, kScanThreads, 0, s>>>(
+                nkeys, n, ncell, w.keyscan, w.partials, cells->start, cells->list, cells->info);
+        } else {
+            k_scan_partials<<<1, kScanThreads, 0, s>>>(nts, w.partials);
+            k_scan_emit<false><<<(unsigned)nts, kScanThreads, 0, s>>>(
+                nkeys, n, ncell, w.keyscan, w.partials, cells->start, cells->list, cells->info);
+        }
+    }
     if (cells->ranges && n > 0) {
         // at most n listed keys, 2 (2n+1)^2 runs each
         const int side = 2 * g->nsub + 1;

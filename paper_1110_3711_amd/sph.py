@@ -475,3 +475,11 @@ class Simulation:
 
     def dev_status(self) -> int:
         return int(self.status.item())
+
+    def check_status(self) -> int:
+        """Device status bits (synchronises); raises on SPH_DEV_BOUNDARY_OUT,
+        which means the sorted state is invalid."""
+        st = self.dev_status()
+        if st & SPH_DEV_BOUNDARY_OUT:
+            raise SphError("a boundary particle lies outside the domain")
+        return st
