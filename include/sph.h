@@ -239,7 +239,7 @@ SPH_API sph_status sph_build_cells(const sph_grid *g, const sph_state *src, sph_
  * address is looked up on the first call on each device.  The call allocates
  * nothing.  Errors: SPH_ERR_ARG as sph_build_cells; SPH_ERR_WORKSPACE (before
  * any device call) when sph_workspace_bytes(g, src->n) exceeds the scratch,
- * e.g. beyond about 2.4M particles on a 475,300-cell grid; SPH_ERR_HIP if the
+ * e.g. beyond about 2.1M particles on a 475,300-cell grid; SPH_ERR_HIP if the
  * scratch address cannot be obtained or a launch fails.  All calls on one
  * device share its scratch and every call rewrites what it reads: calls that
  * overlap in time on one device (two streams, two threads) race and must be

@@ -68,13 +68,16 @@ __device__ inline int64_t sort_elem(int round, int wave, int lane)
     return (int64_t)wave * (kSortTile / (kSortThreads / kWave)) + (int64_t)round * kWave + lane;
 }
 
-// zero (optional, first pass): a u64 array cleared on the side, grid-stride
+// zero, zero32 (optional, first pass): a u64 and a u32 array cleared on the
+// side, grid-stride
 __global__ __launch_bounds__(kSortThreads) void k_radix_hist(int32_t n, int shift, int dbits,
                                                              KeySrc keys,
                                                              uint32_t *__restrict__ hist,
                                                              int nblk, int32_t *dev_status,
                                                              unsigned long long *__restrict__ zero,
-                                                             int64_t nzero)
+                                                             int64_t nzero,
+                                                             uint32_t *__restrict__ zero32,
+                                                             int64_t nzero32)
 {
     __shared__ uint32_t h[kRadixMax];
     const int ndig = 1 << dbits;
@@ -84,6 +87,11 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_hist(int32_t n, int shif
         for (int64_t i = (int64_t)blockIdx.x * kSortThreads + threadIdx.x; i < nzero;
              i += (int64_t)gridDim.x * kSortThreads)
             zero[i] = 0ull;
+    }
+    if (zero32) {
+        for (int64_t i = (int64_t)blockIdx.x * kSortThreads + threadIdx.x; i < nzero32;
+             i += (int64_t)gridDim.x * kSortThreads)
+            zero32[i] = 0u;
     }
     __syncthreads();
     const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
@@ -114,10 +122,15 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_hist(int32_t n, int shif
 // counts (last pass): every key is also counted, ks[key] += count << 32, one
 // atomic per run of equal keys in a wave (the input of the last pass is
 // sorted by the lower digits, so a cell's keys arrive together).
+// next (first of two or more passes): the digit histogram of the next pass,
+// next[digit * nblk + tile of the output slot] += count, taken here from the
+// output slots instead of by a histogram launch of its own (equal keys go to
+// consecutive slots, so again one atomic per run); next starts from zero.
 __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
     int32_t n, int shift, int dbits, KeySrc keys_in, const uint32_t *__restrict__ vals_in,
     uint32_t *__restrict__ keys_out, uint32_t *__restrict__ vals_out,
-    const uint32_t *__restrict__ offs, int nblk, unsigned long long *__restrict__ counts)
+    const uint32_t *__restrict__ offs, int nblk, unsigned long long *__restrict__ counts,
+    uint32_t *__restrict__ next)
 {
     constexpr int NW = kSortThreads / kWave;
     __shared__ uint16_t wcnt[NW][kRadixMax];
@@ -176,9 +189,17 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
     __syncthreads();
 #pragma unroll
     for (int j = 0; j < kSortItems; ++j) {
-        if (rank[j] == 0xffffu) continue;
+        const bool valid = rank[j] != 0xffffu;
         const uint32_t dig = (key[j] >> shift) & dmask;
-        const uint32_t pos = sbase[dig] + wcnt[wave][dig] + rank[j];
+        const uint32_t pos = valid ? sbase[dig] + wcnt[wave][dig] + rank[j] : 0u;
+        if (next) {
+            const uint32_t dn = (key[j] >> (shift + dbits)) & dmask;
+            const uint32_t tn = pos / (uint32_t)kSortTile;
+            add_runs(valid, (tn << kRadixBitsMax) | dn, [&](uint32_t, uint32_t c) {
+                atomicAdd(&next[(int64_t)dn * nblk + tn], c);
+            });
+        }
+        if (!valid) continue;
         keys_out[pos] = key[j];
         vals_out[pos] = val[j];
     }
@@ -475,17 +496,24 @@ hipError_t launch_build_cells(const sph_grid *g, const sph_state *src, sph_state
     uint32_t *kin = nullptr, *vin = nullptr, *kout = w.keys0, *vout = w.vals0;
     const int nblk = nblk_sort(n);
     const int64_t lenks = nkeys + 1;
+    // The first pass's scatter takes the second pass's histogram (into hist2);
+    // a third pass, if any, has a histogram launch of its own.
     bool cleared = false;
-    for (int shift = 0; shift < bits && n > 0; shift += dbits) {
+    const int64_t nhist = ((int64_t)1 << dbits) * nblk;
+    for (int shift = 0, p = 0; shift < bits && n > 0; shift += dbits, ++p) {
         const KeySrc ks{kin, src->cell, src->nb, ncell};
-        k_radix_hist<<<nblk, kSortThreads, 0, s>>>(n, shift, dbits, ks, w.hist, nblk, dev_status,
-                                                   cleared ? nullptr : w.keyscan, lenks);
+        uint32_t *hist = p == 1 ? w.hist2 : w.hist;
+        if (p != 1)
+            k_radix_hist<<<nblk, kSortThreads, 0, s>>>(
+                n, shift, dbits, ks, hist, nblk, dev_status, cleared ? nullptr : w.keyscan, lenks,
+                p == 0 && npass > 1 ? w.hist2 : nullptr, nhist);
         cleared = true;
-        hipError_t e = exclusive_scan<uint32_t>(w.hist, ((int64_t)1 << dbits) * nblk, w.partials, s);
+        hipError_t e = exclusive_scan<uint32_t>(hist, nhist, w.partials, s);
         if (e != hipSuccess) return e;
         const bool last = shift + dbits >= bits;
-        k_radix_scatter<<<nblk, kSortThreads, 0, s>>>(n, shift, dbits, ks, vin, kout, vout, w.hist,
-                                                      nblk, last ? w.keyscan : nullptr);
+        k_radix_scatter<<<nblk, kSortThreads, 0, s>>>(n, shift, dbits, ks, vin, kout, vout, hist,
+                                                      nblk, last ? w.keyscan : nullptr,
+                                                      p == 0 && npass > 1 ? w.hist2 : nullptr);
         if (kin == nullptr) {
             kin = kout;
             vin = vout;

@@ -32,6 +32,7 @@ inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 struct Workspace {
     uint32_t *keys0, *vals0, *keys1, *vals1;  // radix ping-pong [n] each
     uint32_t *hist;                           // [kRadixMax * nblk_sort] digit-major
+    uint32_t *hist2;                          // the same, second pass (filled by the first)
     unsigned long long *partials;             // scan partial sums
     unsigned long long *keyscan;              // [nkeys + 1] packed (count << 32 | nonempty)
     int32_t *counters;                        // [64] work queues and flags
@@ -62,6 +63,7 @@ inline bool layout_workspace(const sph_grid *g, int64_t n, void *base, Workspace
     const size_t o_k1 = take(sizeof(uint32_t) * (size_t)(n > 0 ? n : 1));
     const size_t o_v1 = take(sizeof(uint32_t) * (size_t)(n > 0 ? n : 1));
     const size_t o_h = take(sizeof(uint32_t) * (size_t)kRadixMax * (size_t)(nb > 0 ? nb : 1));
+    const size_t o_h2 = take(sizeof(uint32_t) * (size_t)kRadixMax * (size_t)(nb > 0 ? nb : 1));
     size_t np = scan_partials_needed((int64_t)kRadixMax * nb);
     const size_t np2 = scan_partials_needed(nkeys + 1);
     if (np2 > np) np = np2;
@@ -79,6 +81,7 @@ inline bool layout_workspace(const sph_grid *g, int64_t n, void *base, Workspace
         w->keys1 = (uint32_t *)(b + o_k1);
         w->vals1 = (uint32_t *)(b + o_v1);
         w->hist = (uint32_t *)(b + o_h);
+        w->hist2 = (uint32_t *)(b + o_h2);
         w->partials = (unsigned long long *)(b + o_p);
         w->keyscan = (unsigned long long *)(b + o_ks);
         w->counters = (int32_t *)(b + o_c);
