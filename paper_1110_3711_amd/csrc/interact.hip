@@ -46,6 +46,7 @@ constexpr int kRing = 128;           // per-wave ring of compacted candidates
 constexpr int kMaxRuns = 2 * 25;     // types x (2n+1)^2, n <= 2
 constexpr float kFar = 1.0e30f;      // padding position: never within the support
 constexpr int kXcds = 8;             // MI355X: workgroups are dealt to 8 XCDs round robin
+constexpr int kPad = 3 * kWave;      // padding entries after the placed candidates
 constexpr int kBinBits = 5;          // staged candidates are ordered by 32 bins of x
 constexpr int kBins = 1 << kBinBits;
 
@@ -326,10 +327,10 @@ struct KindTraits {
 template <int TILE, bool BWD, bool STATS, int POS = 0>
 struct PairLds {
     static constexpr int STAGE = (TILE + kThreads - 1) / kThreads;
-    static constexpr int DTILE = POS ? TILE + 2 * kWave : 1;
+    static constexpr int DTILE = POS ? TILE + kPad : 1;
     double sDx[DTILE], sDy[DTILE], sDz[DTILE];  // SPH_POS_ABS64: x_b - centre of the
                                             //   target cell, FP64, + padding
-    float4 sP[TILE + 2 * kWave];            // (offset in target frame, P/rho^2) + padding
+    float4 sP[TILE + kPad];                 // (offset in target frame, P/rho^2) + padding
     float4 sV[TILE];                        // (v, rho - rho0)
     float4 sA[BWD ? TILE : 1];              // backward: (abar, Dbar), abar = 0 on boundary
     alignas(256) uint16_t sRing[kWaves][kRing];  // 256 bytes per wave
@@ -548,9 +549,9 @@ __device__ __forceinline__ void pair_item(const PairConsts &K, const PairArgs &A
         if (STAGE > 2) place(2, j2, q2, bn2, rk2, sx2, kp2);
         if (STAGE > 3) place(3, j3, q3, bn3, rk3, sx3, kp3);
         // padding after the placed candidates: the chunks of a window end
-        // before sBin[kBins] + 2 * kWave
+        // before sBin[kBins] + kPad
         const int32_t nplaced = sBin[kBins];
-        if (threadIdx.x < 2 * kWave) {
+        if (threadIdx.x < kPad) {
             sP[nplaced + threadIdx.x] = make_float4(kFar, kFar, kFar, 0.f);
             if (POS) {
                 S.sDx[nplaced + threadIdx.x] = (double)kFar;
@@ -796,7 +797,8 @@ __device__ __forceinline__ void pair_item(const PairConsts &K, const PairArgs &A
             // are monotone in x), rounded up to whole chunks of 64; entries past
             // the window are real candidates or padding and are tested as usual.
             // Two chunks per iteration, both loaded up front: the second read
-            // ends before sBin[kBins] + 2 * kWave, inside the padding.
+            // ends before sBin[kBins] + 2 * kWave, inside the padding (four
+            // for boundary targets, whose reads end before sBin[kBins] + kPad).
             // (wave-uniform: every lane holds the same target)
             // both bin starts are read before either is used (one LDS round trip)
             const int32_t sb0 = sBin[xbin(pa.x - K.xwin)];
@@ -805,6 +807,29 @@ __device__ __forceinline__ void pair_item(const PairConsts &K, const PairArgs &A
             const int32_t w1 = __builtin_amdgcn_readfirstlane(sb1);
             next_l = slot_of(a + kWaves);  // returns during the scan below
             const int32_t wend = w0 + ((w1 - w0 + kWave - 1) & ~(kWave - 1));
+            if (!FLUID && !POS) {
+                // boundary targets (few per wave, latency-bound): four chunks
+                // per iteration, the last two loaded only inside the window
+                // (their reads end inside the padding)
+                for (int32_t cb0 = w0; cb0 < wend; cb0 += 4 * kWave) {
+                    const float4 c0 = sP[cb0 + lane];
+                    const float4 c1 = sP[cb0 + kWave + lane];
+                    const bool more = cb0 + 2 * kWave < wend;
+                    float4 c2 = c0, c3 = c0;
+                    if (more) {
+                        c2 = sP[cb0 + 2 * kWave + lane];
+                        c3 = sP[cb0 + 3 * kWave + lane];
+                    }
+                    chunk(pa.x - c0.x, pa.y - c0.y, pa.z - c0.z, cb0);
+                    if (cb0 + kWave < wend)
+                        chunk(pa.x - c1.x, pa.y - c1.y, pa.z - c1.z, cb0 + kWave);
+                    if (more) {
+                        chunk(pa.x - c2.x, pa.y - c2.y, pa.z - c2.z, cb0 + 2 * kWave);
+                        if (cb0 + 3 * kWave < wend)
+                            chunk(pa.x - c3.x, pa.y - c3.y, pa.z - c3.z, cb0 + 3 * kWave);
+                    }
+                }
+            } else
             for (int32_t cb0 = w0; cb0 < wend; cb0 += 2 * kWave) {
                 if (POS) {
                     const int i0 = cb0 + lane, i1 = cb0 + kWave + lane;
