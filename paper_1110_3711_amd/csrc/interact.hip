@@ -318,7 +318,7 @@ struct KindTraits {
     static constexpr bool fluid = KIND == kFwdFluid || KIND == kBwdFluid || fused;  // first list
     // LDS per candidate: 32 B (forward), 48 B (backward), 56 B (forward with
     // FP64 positions)
-    static constexpr int tile = bwd ? 1280 : (POS ? 1024 : kTile);
+    static constexpr int tile = bwd ? 1408 : (POS ? 1024 : kTile);
     static constexpr int first = fused ? (bwd ? kBwdFluid : kFwdFluid) : KIND;
     static constexpr int second = bwd ? kBwdBound : kFwdBound;
 };
