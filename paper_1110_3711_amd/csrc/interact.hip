@@ -49,6 +49,11 @@ constexpr int kXcds = 8;             // MI355X: workgroups are dealt to 8 XCDs r
 constexpr int kPad = 3 * kWave;      // padding entries after the placed candidates
 constexpr int kBinBits = 5;          // staged candidates are ordered by 32 bins of x
 constexpr int kBins = 1 << kBinBits;
+// work queue of a list: kXcds chunk counters, the pool counter, the flag word
+// (counter slots, kCounterStride ints apart)
+constexpr int kQPool = kXcds;
+constexpr int kQFlags = kXcds + 1;
+constexpr int kPool64 = 10;          // the pool: the last 10/64 of the list
 
 struct RunTable {
     int32_t nruns;
@@ -967,20 +972,39 @@ __attribute__((amdgpu_waves_per_eu(!STATS ? 4 : 1, 4))) void k_interact(
         nitems = min(max(A.counts[0], 0), K.n);
     }
     unsigned long long p1 = 0, p2 = 0;  // wave-uniform pair counts of the two lists
-    // XCD-aware dynamic schedule: the work list is cut into kXcds contiguous
-    // chunks with one counter each; workgroup b starts on chunk b mod kXcds
-    // (the XCD it runs on), so neighbouring cells share that XCD's L2, and
-    // moves to the next chunk when one is exhausted.  Fused launches interleave
-    // the second list (one counter): after every `mix` items of the first list
-    // a workgroup takes one of the second, so its short, latency-bound items
-    // overlap with the compute-bound ones instead of forming the tail; once the
-    // first list is exhausted the second is drained.  The counters only grow,
-    // so every workgroup leaves once both lists are exhausted.
+    // XCD-aware dynamic schedule of the first list, in three phases:
+    //  * home: its first (64 - kPool64)/64 is cut into kXcds contiguous chunks
+    //    with one counter each, and workgroup b (dealt to XCD b mod kXcds)
+    //    draws from chunk b mod kXcds, so cells with common stencil neighbours
+    //    run on the XCD whose L2 holds them;
+    //  * pool: the rest of the list behind one counter of all workgroups, so
+    //    the XCDs whose chunk ends early take more of it;
+    //  * steal: then from the chunks that still hold more than four items per
+    //    workgroup of their own (flag word: bit x is set by the draw that
+    //    leaves that many in chunk x), which only happens when the chunks'
+    //    work differs widely (clustered layouts).
+    // No workgroup walks through exhausted chunks with atomics: at the end of
+    // a launch every workgroup would do so at once.  Fused launches interleave
+    // the second list (one counter): after every `mix` items of the first
+    // list a workgroup takes one of the second, so its short, latency-bound
+    // items overlap with the compute-bound ones instead of forming the tail;
+    // once the first list is exhausted the second is drained.  The counters
+    // only grow, so every workgroup leaves once both lists are exhausted: each
+    // chunk is drained by the workgroups of its own XCD at least.
     const int32_t n2 = T::fused ? min(max(A.counts2[0], 0), K.n) : 0;
     const int32_t mix = nitems / (n2 + 1);
     const int home = blockIdx.x % kXcds;
-    int tries = 0;       // exhausted chunks of the first list (thread 0 only)
-    int32_t since = 0;   // first-list items since the last second-list item (thread 0)
+    const int32_t plen = (int32_t)(((int64_t)nitems * kPool64) / 64);
+    const int32_t m = nitems - plen;  // chunks cover [0, m), the pool [m, nitems)
+    const int32_t lo = (int32_t)(((int64_t)m * home) / kXcds);
+    const int32_t hi = (int32_t)(((int64_t)m * (home + 1)) / kXcds);
+    int32_t *const flags = A.queue + kQFlags * kCounterStride;
+    const int32_t near = max(4 * (int32_t)gridDim.x / kXcds, 1);
+    // thread 0 only: schedule state
+    bool home_done = false, pool_done = false, ex_read = false;
+    int steal = 1;       // next chunk to steal from: home + steal
+    unsigned ex = 0;     // chunks known to hold at most `near` unclaimed items
+    int32_t since = 0;   // first-list items since the last second-list item
     bool done2 = !T::fused;
     for (;;) {
         if (threadIdx.x == 0) {
@@ -996,17 +1020,50 @@ __attribute__((amdgpu_waves_per_eu(!STATS ? 4 : 1, 4))) void k_interact(
                     done2 = true;
                 }
             }
-            while (it < 0 && tries < kXcds) {
-                const int x = (home + tries) % kXcds;
-                const int32_t lo = (int32_t)(((int64_t)nitems * x) / kXcds);
-                const int32_t hi = (int32_t)(((int64_t)nitems * (x + 1)) / kXcds);
-                const int32_t k = atomicAdd(A.queue + x, 1);
+            if (it < 0 && !home_done) {
+                const int32_t k = atomicAdd(A.queue + home * kCounterStride, 1);
                 if (k < hi - lo) {
                     it = lo + k;
                     ++since;
-                    break;
+                    if (k == max(hi - lo - 1 - near, 0)) atomicOr(flags, 1 << home);
+                } else {
+                    home_done = true;
                 }
-                ++tries;
+            }
+            if (it < 0 && !pool_done) {
+                const int32_t k = atomicAdd(A.queue + kQPool * kCounterStride, 1);
+                if (k < plen) {
+                    it = m + k;
+                    ++since;
+                } else {
+                    pool_done = true;
+                }
+            }
+            if (it < 0 && steal < kXcds) {
+                if (!ex_read) {
+                    ex_read = true;
+                    ex = (unsigned)__hip_atomic_load(flags, __ATOMIC_RELAXED,
+                                                     __HIP_MEMORY_SCOPE_AGENT);
+                }
+                while (steal < kXcds) {
+                    const int x = (home + steal) % kXcds;
+                    if (!((ex >> x) & 1u)) {
+                        const int32_t xlo = (int32_t)(((int64_t)m * x) / kXcds);
+                        const int32_t xhi = (int32_t)(((int64_t)m * (x + 1)) / kXcds);
+                        const unsigned f = (unsigned)__hip_atomic_load(
+                            flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        const int32_t k = atomicAdd(A.queue + x * kCounterStride, 1);
+                        ex |= f;
+                        if (k < xhi - xlo) {
+                            it = xlo + k;
+                            ++since;
+                            if (k == max(xhi - xlo - 1 - near, 0)) atomicOr(flags, 1 << x);
+                            break;
+                        }
+                        ex |= 1u << x;
+                    }
+                    ++steal;
+                }
             }
             if (it < 0 && !done2) {
                 const int32_t k = atomicAdd(A.queue2, 1);
@@ -1034,9 +1091,25 @@ __attribute__((amdgpu_waves_per_eu(!STATS ? 4 : 1, 4))) void k_interact(
             pair_item<T::second, STATS, KER, TENS, POS>(K, A, S, C, key, p2);
         }
     }
-    if (A.npairs && C.lane == 0) {
-        if (p1) atomicAdd(A.npairs + (T::fluid ? 0 : 1), p1);
-        if (p2) atomicAdd(A.npairs + 1, p2);
+    if (A.npairs) {
+        // one atomic per workgroup and list: the waves' counts are summed in
+        // LDS (the rings are free once the item loop has ended); one per wave
+        // on the same address lengthened the fused launch by 5%
+        unsigned long long *sp = (unsigned long long *)&S.sRing[0][0];
+        if (C.lane == 0) {
+            sp[C.wave] = p1;
+            sp[kWaves + C.wave] = p2;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            unsigned long long t1 = 0, t2 = 0;
+            for (int w = 0; w < kWaves; ++w) {
+                t1 += sp[w];
+                t2 += sp[kWaves + w];
+            }
+            if (t1) atomicAdd(A.npairs + (T::fluid ? 0 : 1), t1);
+            if (t2) atomicAdd(A.npairs + 1, t2);
+        }
     }
 }
 
@@ -1089,18 +1162,29 @@ __global__ void k_bound_filter(PairConsts K, const int32_t *__restrict__ start,
             }
         }
     }
+    // one atomic per wavefront: the first live lane reserves the wave's slots
     const int32_t nbc = min(max(info[0], 0), K.n);
+    const int lane = lane_id();
     for (int32_t i = gid; i < nbc; i += stride) {
         const int32_t key = min(max(list[i], 0), K.ncell - 1);
         const int32_t total = K.nsub == 1 ? fluid_in_reach<1>(K, start, key)
                                           : fluid_in_reach<2>(K, start, key);
-        if (total > 0) active[atomicAdd(nactive, 1)] = key;
+        const unsigned long long live = ballot(true);
+        const unsigned long long m = ballot(total > 0);
+        if (m) {
+            const int leader = __ffsll((long long)live) - 1;
+            int32_t base = 0;
+            if (lane == leader) base = atomicAdd(nactive, __popcll(m));
+            base = __shfl(base, leader, kWave);
+            if (total > 0) active[base + (int32_t)lane_rank(m)] = key;
+        }
     }
 }
 
+// clears counter slots [0, count) (count <= 64), kCounterStride ints apart
 __global__ void k_zero_counters(int32_t *q, int count)
 {
-    if ((int)threadIdx.x < count) q[threadIdx.x] = 0;
+    if ((int)threadIdx.x < count) q[threadIdx.x * kCounterStride] = 0;
 }
 
 
@@ -1190,7 +1274,9 @@ static hipError_t launch_one(const PairConsts &K, const PairArgs &A, hipStream_t
     if (e != hipSuccess) return e;
     if (cus <= 0) cus = 1;
     if (occ <= 0) occ = 1;
-    k_interact<KIND, STATS, KER, TENS, POS><<<cus * occ, kThreads, 0, s>>>(K, A);
+    // every chunk of the work queue needs a workgroup of its own XCD
+    const int grid = cus * occ < kXcds ? kXcds : cus * occ;
+    k_interact<KIND, STATS, KER, TENS, POS><<<grid, kThreads, 0, s>>>(K, A);
     return hipGetLastError();
 }
 
@@ -1258,31 +1344,33 @@ hipError_t launch_interact(const sph_grid *g, const sph_params *p, const sph_sta
     A.visc = visc;
     A.npairs = npairs;
     A.stats = nbr_stats;
-    // counters: [0, 8) first-list queues, [8, 16) boundary queues of a separate
-    // boundary launch or [8] the boundary counter of the fused launch, [16]
-    // active boundary cells
+    // counter slots: [0, 10) the first list's queue (chunks, pool, flags),
+    // [16, 26) the queue of a separate boundary launch or [16] the boundary
+    // counter of the fused launch, [32] active boundary cells
     const bool stats = nbr_stats != nullptr;
-    k_zero_counters<<<1, 64, 0, s>>>(w.counters, 17);
+    int32_t *const q = w.counters;
+    constexpr int S = kCounterStride;
+    k_zero_counters<<<1, 64, 0, s>>>(q, 33);
     if (parts & SPH_PI_BOUNDARY)
         k_bound_filter<<<256, 256, 0, s>>>(K, cells->start, cells->list, cells->info, w.active,
-                                           w.counters + 16, (float4 *)ace, visc, nbr_stats);
+                                           q + 32 * S, (float4 *)ace, visc, nbr_stats);
     if (parts == SPH_PI_ALL) {
-        A.queue = w.counters;
+        A.queue = q;
         A.items2 = w.active;
-        A.counts2 = w.counters + 16;
-        A.queue2 = w.counters + 8;
+        A.counts2 = q + 32 * S;
+        A.queue2 = q + 16 * S;
         return launch_kind<kFwdAll>(K, A, stats, s);
     }
     hipError_t e = hipSuccess;
     if (parts & SPH_PI_FLUID) {
-        A.queue = w.counters;
+        A.queue = q;
         e = launch_kind<kFwdFluid>(K, A, stats, s);
         if (e != hipSuccess) return e;
     }
     if (parts & SPH_PI_BOUNDARY) {
         A.items = w.active;
-        A.counts = w.counters + 16;
-        A.queue = w.counters + 8;
+        A.counts = q + 32 * S;
+        A.queue = q + 16 * S;
         e = launch_kind<kFwdBound>(K, A, stats, s);
     }
     return e;
@@ -1336,15 +1424,18 @@ hipError_t launch_interact_backward(const sph_grid *g, const sph_params *p, cons
     A.xbar = (float4 *)pos_bar;
     A.vbar = (float4 *)velrho_bar;
     A.alpha_part = w.alpha_part;
-    // counters: [24, 32) fluid queues, [32] boundary counter, [40] active cells
-    k_zero_counters<<<1, 64, 0, s>>>(w.counters + 24, 17);
+    // counter slots: [40, 50) the fluid list's queue, [56] boundary counter,
+    // [60] active cells
+    int32_t *const q = w.counters;
+    constexpr int S = kCounterStride;
+    k_zero_counters<<<1, 64, 0, s>>>(q + 40 * S, 21);
     // boundary gatherers: only cells with fluid in reach have non-zero terms
     k_bound_filter<<<256, 256, 0, s>>>(K, cells->start, cells->list, cells->info, w.active,
-                                       w.counters + 40, nullptr, nullptr, nullptr);
-    A.queue = w.counters + 24;
+                                       q + 60 * S, nullptr, nullptr, nullptr);
+    A.queue = q + 40 * S;
     A.items2 = w.active;
-    A.counts2 = w.counters + 40;
-    A.queue2 = w.counters + 32;
+    A.counts2 = q + 60 * S;
+    A.queue2 = q + 56 * S;
     hipError_t e = launch_kind<kBwdAll>(K, A, false, s);
     if (e != hipSuccess) return e;
     int nblk = (int)(((int64_t)st->n + kReduceThreads - 1) / kReduceThreads);

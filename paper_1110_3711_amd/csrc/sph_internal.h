@@ -20,6 +20,11 @@ constexpr int kScanTile = kScanThreads * kScanItems;
 constexpr int kReduceThreads = 256;
 constexpr int kReduceBlocksMax = 1024;
 constexpr int kConsSums = 16;        // conservation sums (sph_conservation)
+// work-queue counters of the pair kernels: kCounterSlots counters, each on a
+// 128-byte line of its own (atomics of many workgroups on one line queue
+// behind each other)
+constexpr int kCounterStride = 32;
+constexpr int kCounterSlots = 64;
 
 inline int64_t ncell_of(const sph_grid *g)
 {
@@ -35,7 +40,7 @@ struct Workspace {
     uint32_t *hist2;                          // the same, second pass (filled by the first)
     unsigned long long *partials;             // scan partial sums
     unsigned long long *keyscan;              // [nkeys + 1] packed (count << 32 | nonempty)
-    int32_t *counters;                        // [64] work queues and flags
+    int32_t *counters;                        // [kCounterSlots * kCounterStride] work queues
     int32_t *active;                          // [n] boundary cells with fluid in reach
     float *alpha_part;                        // [n] per-slot alpha adjoint
     double *reduce;                           // [kConsSums * kReduceBlocksMax] block partials
@@ -69,7 +74,7 @@ inline bool layout_workspace(const sph_grid *g, int64_t n, void *base, Workspace
     if (np2 > np) np = np2;
     const size_t o_p = take(sizeof(unsigned long long) * np);
     const size_t o_ks = take(sizeof(unsigned long long) * (size_t)(nkeys + 1));
-    const size_t o_c = take(sizeof(int32_t) * 64);
+    const size_t o_c = take(sizeof(int32_t) * kCounterSlots * kCounterStride);
     const size_t o_a = take(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
     const size_t o_ap = take(sizeof(float) * (size_t)(n > 0 ? n : 1));
     const size_t o_r = take(sizeof(double) * kConsSums * kReduceBlocksMax);
