@@ -130,3 +130,40 @@ def check_sets_in_band(count, hsum, inner, outer, max_band=16):
         ok = any(sum(hb[i] for i in c) % (1 << 32) == want for c in combinations(range(len(band)), k))
         assert ok, f"target {a}: no subset of its {len(band)} band pairs matches the device set"
     return len(tied), int((no - ni).sum())
+
+
+def check_every_cell_once(lay, label, nsub=1):
+    """The pair kernel's work queue hands out every cell exactly once: with
+    every output slot pre-filled with NaN, the fused forward launch writes
+    every slot (a cell never taken leaves NaN), and its directed pair count
+    equals the sum of the per-target counts of the statistics kernel on the
+    same state (a cell taken twice would add its pairs twice to the count,
+    while its per-target outputs would only be written again)."""
+    import torch
+
+    from paper_1110_3711_amd import sph
+
+    sim = sph.Simulation(lay, nsub=nsub)
+    sim.build_cells()
+    sim.ace.fill_(float("nan"))
+    sim.visc.fill_(float("nan"))
+    sim.npairs.zero_()
+    sim.interact()
+    torch.cuda.synchronize()
+    total = int(sim.npairs.sum().item())
+    ace = sim.by_id(sim.ace)
+    visc = sim.by_id(sim.visc)
+    st = torch.zeros(2 * lay.n, dtype=torch.int32, device=sim.device)
+    sim.npairs.zero_()
+    sim.interact(stats=st)
+    torch.cuda.synchronize()
+    counted = int(st.view(-1, 2)[:, 0].to(torch.int64).sum().item())
+    total_stats = int(sim.npairs.sum().item())
+    unwritten = int((~np.isfinite(ace)).any(axis=1).sum() + (~np.isfinite(visc)).sum())
+    del sim
+    torch.cuda.empty_cache()
+    print(f"  {label}: {total:,} directed pairs (default kernel), {counted:,} summed per target "
+          f"(statistics kernel, which counts {total_stats:,}); unwritten output slots {unwritten}",
+          flush=True)
+    assert unwritten == 0
+    assert total == counted == total_stats

@@ -23,7 +23,7 @@ import time
 import numpy as np
 import pytest
 
-from _helpers import elem_err, grid_tuple, oracle_view, rel_l2
+from _helpers import check_every_cell_once, elem_err, grid_tuple, oracle_view, rel_l2
 from sph_inputs import CLUSTER_SEED, SEED_BASE, named_case, refine
 
 pytestmark = pytest.mark.gpu
@@ -198,3 +198,11 @@ def test_clustered_step_timing(clustered):
     s2 = _timed_steps(clustered, pos64=True)
     del s2
     torch.cuda.empty_cache()
+
+
+def test_clustered_every_cell_once(clustered):
+    """The work queue where the work is very unevenly spread along the cell
+    list, so that workgroups steal from the chunks of other XCDs (see the
+    helper)."""
+    print(f"work queue clustered n={clustered.n}", flush=True)
+    check_every_cell_once(clustered, "dam_break_4m_clustered")

@@ -9,7 +9,7 @@ import dataclasses
 import numpy as np
 import pytest
 
-from _helpers import grid_tuple, oracle_view, parity
+from _helpers import check_every_cell_once, grid_tuple, oracle_view, parity
 from sph_inputs import SEED_BASE, dam_break
 
 pytestmark = pytest.mark.gpu
@@ -114,3 +114,12 @@ def test_bench_layout_parity_along_oracle_trajectory(ora):
         print(f"large trajectory: step {k}, max |v| {vmax:.3f} m/s", flush=True)
         e = _subset_parity(ora, L, 1, seed=k)
         assert max(e) <= 1e-4
+
+
+def test_bench_layout_every_cell_once():
+    """The work queue at the bench size: the chunks of the XCDs, then the
+    shared pool of the last cells of the list (see the helper)."""
+    lay = dam_break(0.002, SEED_BASE + 2, vel_sigma=0.05, vel_seed=SEED_BASE + 20,
+                    name="dam_break_1m+v")
+    print(f"work queue dam_break_1m+v n={lay.n}", flush=True)
+    check_every_cell_once(lay, "dam_break_1m+v")
