@@ -42,7 +42,7 @@ namespace sph {
 constexpr int kThreads = 512;
 constexpr int kWaves = kThreads / kWave;
 constexpr int kTile = 2048;          // candidates staged per pass (multiple of 64)
-constexpr int kRing = 128;           // per-wave ring of compacted candidates
+constexpr int kRing = 256;           // per-wave ring of compacted candidates
 constexpr int kMaxRuns = 2 * 25;     // types x (2n+1)^2, n <= 2
 constexpr float kFar = 1.0e30f;      // padding position: never within the support
 constexpr int kXcds = 8;             // MI355X: workgroups are dealt to 8 XCDs round robin
@@ -338,7 +338,7 @@ struct PairLds {
     float4 sP[TILE + kPad];                 // (offset in target frame, P/rho^2) + padding
     float4 sV[TILE];                        // (v, rho - rho0)
     float4 sA[BWD ? TILE : 1];              // backward: (abar, Dbar), abar = 0 on boundary
-    alignas(256) uint16_t sRing[kWaves][kRing];  // 256 bytes per wave
+    alignas(512) uint16_t sRing[kWaves][kRing];  // 512 bytes per wave
     uint16_t sTrash[kWaves][kWave];         // rejected candidates land here
     union {
         uint16_t sMap[TILE];                // fluid targets: staging index -> sorted slot
@@ -352,7 +352,7 @@ struct PairLds {
     int32_t sKind;                          // fused launches: 0 fluid item, 1 boundary item
 };
 
-// per-lane constants: LDS byte addresses of this wave's ring (256-aligned),
+// per-lane constants: LDS byte addresses of this wave's ring (512-aligned),
 // the lane's first read entry and trash slot, the staged arrays
 struct LaneCtx {
     int lane, wave;
@@ -777,9 +777,11 @@ __device__ __forceinline__ void pair_item(const PairConsts &K, const PairArgs &A
             };
 
             // test one chunk of 64 staged candidates; survivors go to the ring as
-            // byte offsets of their staged entries, full batches of 64 are
-            // evaluated at once.  The ring holds kRing entries in 256 bytes, so
-            // slot k sits at rbase | (2 k mod 256).
+            // byte offsets of their staged entries, and full batches of 64 are
+            // evaluated after every two chunks (drain below; checking after
+            // every chunk cost 1.6% of the fused stage in scalar instructions
+            // and branches).  The ring holds kRing entries in 512 bytes, so
+            // slot k sits at rbase | (2 k mod 512).
             auto chunk = [&](float rx, float ry, float rz, int32_t cb0) {
                 const float r2 = __builtin_fmaf(rz, rz, __builtin_fmaf(ry, ry, rx * rx));
                 const bool pass = r2 < K.rc2;
@@ -788,13 +790,17 @@ __device__ __forceinline__ void pair_item(const PairConsts &K, const PairArgs &A
                 // their own trash slot
                 int rk = (int)lane_rank(m);
                 asm volatile("" : "+v"(rk));
-                const uint32_t w = ((uint32_t)(2 * (wp + rk)) & 0xFEu) | rbase;
+                const uint32_t w = ((uint32_t)(2 * (wp + rk)) & 0x1FEu) | rbase;
                 *(lds_u16 *)(uintptr_t)(pass ? w : taddr) = (uint16_t)(lane16 + ((uint32_t)cb0 << 4));
                 wp += __popcll(m);
-                if (wp - rp >= kWave) {
+            };
+            // evaluate every full batch of 64 in the ring (at most two after
+            // two chunks: fewer than 64 + 128 entries pending)
+            auto drain = [&]() {
+                while (wp - rp >= kWave) {
                     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
                     pair(*(const lds_u16 *)(uintptr_t)raddr);
-                    raddr ^= 2u * kWave;
+                    raddr = ((raddr + 2u * kWave) & 0x1FFu) | rbase;
                     rp += kWave;
                 }
             };
@@ -828,10 +834,12 @@ __device__ __forceinline__ void pair_item(const PairConsts &K, const PairArgs &A
                     chunk(pa.x - c0.x, pa.y - c0.y, pa.z - c0.z, cb0);
                     if (cb0 + kWave < wend)
                         chunk(pa.x - c1.x, pa.y - c1.y, pa.z - c1.z, cb0 + kWave);
+                    drain();
                     if (more) {
                         chunk(pa.x - c2.x, pa.y - c2.y, pa.z - c2.z, cb0 + 2 * kWave);
                         if (cb0 + 3 * kWave < wend)
                             chunk(pa.x - c3.x, pa.y - c3.y, pa.z - c3.z, cb0 + 3 * kWave);
+                        drain();
                     }
                 }
             } else
@@ -850,6 +858,7 @@ __device__ __forceinline__ void pair_item(const PairConsts &K, const PairArgs &A
                     if (cb0 + kWave < wend)
                         chunk(pa.x - c1.x, pa.y - c1.y, pa.z - c1.z, cb0 + kWave);
                 }
+                drain();
             }
             if (wp > rp) {
                 __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
